@@ -1,0 +1,212 @@
+/*
+ * harpia.h -- C ABI of libharpia, an MI355X (gfx950) library of chunked,
+ * halo-padded 3D volumetric filters: Gaussian smoothing and grayscale /
+ * binary erosion, dilation, opening and closing (Section III-C of the
+ * paper lists these filters among the library's CUDA algorithms), run chunk
+ * by chunk under a strict device-memory budget so that volumes larger than
+ * the budget still run (Section III-D, chunked processing).
+ *
+ * Volumes
+ *   A volume is a dense C-ordered array [nz][ny][nx] (x contiguous, z
+ *   slowest; chunks split along z as in Section III-D).  shape[] and every
+ *   other per-axis array are ordered {z, y, x}.
+ *
+ * Pointers and ownership (Section I contribution 2, Section IV-C: the
+ * library controls all device memory and releases it when a task ends)
+ *   - `in` / `out` may both be device pointers (resident path: the call is
+ *     asynchronous on ex->stream, no host<->device traffic) or both host
+ *     pointers (streamed path: the library copies halo-padded chunks to the
+ *     device, filters them and copies the core back; the call returns when
+ *     `out` is complete).  Pinned host memory is copied by DMA directly;
+ *     pageable host memory goes through pinned bounce buffers.
+ *   - The caller owns `in` and `out`.  The library keeps no pointer after a
+ *     call returns and holds no device memory between calls: every device
+ *     byte it allocates is freed before the call returns (device path: after
+ *     synchronising ex->stream if it had to allocate).
+ *   - `in` and `out` must not overlap (HARPIA_ERR_ALIAS).
+ *
+ * Errors
+ *   Every function returns a harpia_status; on error the thread-local
+ *   message from harpia_last_error() says why, `out` is unspecified, and no
+ *   device memory stays allocated.  Arguments are validated before any
+ *   device work.
+ *
+ * Boundary
+ *   Every filter uses half-sample symmetric reflection at the volume faces
+ *   (index -1 reads voxel 0, index n reads voxel n-1; repeated for radii
+ *   larger than the volume).  For erosion and dilation by box and ball
+ *   elements this equals ignoring offsets outside the volume.
+ *
+ * Determinism
+ *   Results are bitwise identical across runs and across chunk plans.
+ *
+ * Thread safety: every function may be called from several host threads.
+ */
+#ifndef HARPIA_H
+#define HARPIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum harpia_status {
+    HARPIA_OK = 0,
+    HARPIA_ERR_ARG = -1,         /* invalid shape, sigma, radius, pointer... */
+    HARPIA_ERR_DTYPE = -2,       /* unsupported dtype or dtype pair */
+    HARPIA_ERR_BUDGET = -3,      /* not even the smallest chunk fits */
+    HARPIA_ERR_OOM = -4,         /* a device or pinned allocation failed */
+    HARPIA_ERR_HIP = -5,         /* a HIP runtime call failed */
+    HARPIA_ERR_ALIAS = -6,       /* in and out overlap */
+    HARPIA_ERR_UNSUPPORTED = -7  /* valid request this build does not run */
+} harpia_status;
+
+typedef enum harpia_dtype {
+    HARPIA_U8 = 0,
+    HARPIA_U16 = 1,
+    HARPIA_F32 = 2,
+    HARPIA_F16 = 3,   /* IEEE binary16 */
+    HARPIA_BF16 = 4   /* bfloat16 */
+} harpia_dtype;
+
+/* Structuring elements.  BOX: |dz| <= rz, |dy| <= ry, |dx| <= rx.
+ * BALL: dz^2 + dy^2 + dx^2 <= r^2 (isotropic: radius[0..2] must be equal). */
+typedef enum harpia_se { HARPIA_SE_BOX = 0, HARPIA_SE_BALL = 1 } harpia_se;
+
+typedef enum harpia_border { HARPIA_BORDER_REFLECT = 0 } harpia_border;
+
+typedef enum harpia_morph_op { HARPIA_ERODE = 0, HARPIA_DILATE = 1 } harpia_morph_op;
+
+/* harpia_exec.flags */
+#define HARPIA_F_BINARY 0x1u        /* morphology: binarise the input as v != 0
+                                       (unless a threshold is given); output
+                                       is uint8 {0, 1} */
+#define HARPIA_F_FORCE_CHUNKED 0x2u /* device path: use the chunk engine even
+                                       when the whole volume fits the budget */
+
+/* Optional per-call statistics (filled when harpia_exec.stats != NULL). */
+typedef struct harpia_stats {
+    int64_t n_chunks;          /* chunks executed */
+    int64_t bytes_h2d;         /* host -> device bytes copied */
+    int64_t bytes_d2h;         /* device -> host bytes copied */
+    int64_t peak_device_bytes; /* library-owned device bytes at peak */
+    int64_t budget_bytes;      /* budget the call ran under */
+    double wall_ms;            /* host wall time of the call */
+} harpia_stats;
+
+/* Execution options; a NULL harpia_exec* means all defaults. */
+typedef struct harpia_exec {
+    size_t device_budget_bytes; /* cap on library device memory; 0 => use
+                                   budget_fraction x free device memory */
+    double budget_fraction;     /* fraction of free device memory reserved
+                                   for chunks (Section III-D, step 1);
+                                   0 => HARPIA_DEFAULT_BUDGET_FRACTION */
+    int64_t chunk[3];           /* core chunk extent {z, y, x}; {0, 0, 0} =>
+                                   the planner picks the deepest z-slab that
+                                   fits (Section III-D, step 2) */
+    void *stream;               /* hipStream_t of device-pointer calls; NULL
+                                   => the default (null) stream */
+    uint32_t flags;             /* HARPIA_F_* */
+    harpia_stats *stats;        /* optional output */
+} harpia_exec;
+
+#define HARPIA_DEFAULT_BUDGET_FRACTION 0.5
+
+/* A chunk plan (Section III-D, steps 1 and 2). */
+typedef struct harpia_plan {
+    int64_t shape[3];      /* volume */
+    int64_t core[3];       /* core chunk extent (last chunk per axis may be
+                              smaller) */
+    int64_t grid[3];       /* chunks per axis */
+    int32_t halo[3];       /* halo per side per axis */
+    int32_t n_buffers;     /* buffer sets in flight (copy/compute overlap) */
+    int64_t n_chunks;      /* grid[0] * grid[1] * grid[2] */
+    size_t device_bytes;   /* device bytes the plan allocates (<= budget) */
+    size_t budget_bytes;   /* budget the plan was made for */
+} harpia_plan;
+
+/* Thread-local message of the last failing call on this thread ("" if the
+ * last call succeeded).  Valid until the next call on the same thread. */
+const char *harpia_last_error(void);
+
+/* Library version string, e.g. "harpia 0.1.0 gfx950". */
+const char *harpia_version(void);
+
+/* Truncation radius of a Gaussian: (int)(truncate * sigma + 0.5).
+ * Returns -1 if sigma <= 0 or truncate < 0. */
+int32_t harpia_gauss_radius(double sigma, double truncate);
+
+/* Plan the chunking of a volume of `shape` whose filter needs `halo` voxels
+ * per side (Section III-D: query free memory, reserve a fixed fraction,
+ * compute the largest chunk that fits with its padding).  in_t / out_t give
+ * the bytes per voxel of the staged input and output chunks.  ex may be
+ * NULL.  With ex->device_budget_bytes != 0 no device is queried, so this
+ * call works without a GPU.
+ * Errors: HARPIA_ERR_ARG (shape <= 0, halo < 0, out == NULL),
+ *         HARPIA_ERR_DTYPE, HARPIA_ERR_BUDGET (a 1-slice chunk with its halo
+ *         does not fit), HARPIA_ERR_HIP (free-memory query failed). */
+harpia_status harpia_chunk_plan(const int64_t shape[3], harpia_dtype in_t,
+                                harpia_dtype out_t, const int32_t halo[3],
+                                const harpia_exec *ex, harpia_plan *out);
+
+/* Gaussian smoothing (Section III-C, filtering suite):
+ *   out = G_sigma * in, separable, taps w_k = exp(-k^2 / (2 s^2)) / sum,
+ *   k = -r..r with r = (int)(truncate * s + 0.5) per axis, taps generated in
+ *   FP64 and rounded to FP32, FP32 accumulation, reflect boundary.
+ * sigma[3] per axis {z, y, x}, each > 0; truncate >= 0 (3.0 is usual).
+ * dtype pairs (in -> out): F32->F32, U16->F32, U8->F32, F16->F16, F16->F32,
+ *   BF16->BF16, BF16->F32.  16-bit outputs are rounded to nearest even.
+ * Errors: ARG, DTYPE, ALIAS, BUDGET, OOM, HIP. */
+harpia_status harpia_gaussian3d(const void *in, harpia_dtype in_t, void *out,
+                                harpia_dtype out_t, const int64_t shape[3],
+                                const double sigma[3], double truncate,
+                                harpia_border border, const harpia_exec *ex);
+
+/* Erosion (min over the structuring element placed at each voxel) and
+ * dilation (max) (Section III-C, label editing module).
+ * t: dtype of `in`.  Grayscale: out has dtype t, results are exact.
+ * Binary: if `threshold` is not NaN the input is binarised as in > threshold
+ * (strict; the comparison is exact in the input's type), else with
+ * HARPIA_F_BINARY as in != 0; `out` is then uint8 {0, 1}.
+ * radius[3] >= 0 per axis {z, y, x}; BALL needs equal radii.
+ * Errors: ARG, DTYPE, ALIAS, BUDGET, OOM, HIP, UNSUPPORTED. */
+harpia_status harpia_erode3d(const void *in, void *out, harpia_dtype t,
+                             const int64_t shape[3], harpia_se se,
+                             const int32_t radius[3], double threshold,
+                             harpia_border border, const harpia_exec *ex);
+
+harpia_status harpia_dilate3d(const void *in, void *out, harpia_dtype t,
+                              const int64_t shape[3], harpia_se se,
+                              const int32_t radius[3], double threshold,
+                              harpia_border border, const harpia_exec *ex);
+
+/* Erosion and dilation with one element from a single read of the input
+ * (both outputs of the label-editing module's morphology; their difference
+ * is the morphological gradient).  Same rules as harpia_erode3d; the two
+ * outputs must not overlap each other or `in`. */
+harpia_status harpia_erode_dilate3d(const void *in, void *out_erode,
+                                    void *out_dilate, harpia_dtype t,
+                                    const int64_t shape[3], harpia_se se,
+                                    const int32_t radius[3], double threshold,
+                                    harpia_border border,
+                                    const harpia_exec *ex);
+
+/* A chain of erosions / dilations with one element, e.g. opening =
+ * {HARPIA_ERODE, HARPIA_DILATE} and closing = {HARPIA_DILATE, HARPIA_ERODE}
+ * (Section III-C lists both).  Each step is computed over the whole volume
+ * before the next (the halo is the sum of the radii); the binarisation
+ * rules of harpia_erode3d apply to the first step.  1 <= n_ops <= 8. */
+harpia_status harpia_morph3d(const void *in, void *out, harpia_dtype t,
+                             const int64_t shape[3],
+                             const harpia_morph_op *ops, int32_t n_ops,
+                             harpia_se se, const int32_t radius[3],
+                             double threshold, harpia_border border,
+                             const harpia_exec *ex);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HARPIA_H */

@@ -1,0 +1,260 @@
+"""Harpia-style chunked volumetric filters for MI355X (gfx950).
+
+Python layer over libharpia (include/harpia.h).  Volumes are [nz, ny, nx]
+arrays: CUDA/HIP torch tensors run resident on the current torch stream;
+CPU torch tensors and numpy arrays run through the library's chunk engine
+(copied to the GPU chunk by chunk under a device-memory budget).  All
+filtering happens in the HIP library; this package only marshals arguments
+and allocates outputs.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import _lib
+from ._lib import HarpiaError, harpia_plan, harpia_stats
+
+__all__ = ["gaussian", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
+           "plan", "gauss_radius", "version", "HarpiaError", "harpia_stats", "Exec"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+_NP_DT = {np.dtype(np.uint8): _lib.HARPIA_U8, np.dtype(np.uint16): _lib.HARPIA_U16,
+          np.dtype(np.float32): _lib.HARPIA_F32, np.dtype(np.float16): _lib.HARPIA_F16}
+_DT_NP = {v: k for k, v in _NP_DT.items()}
+
+
+def _torch_dt():
+    t = _torch()
+    return {t.uint8: _lib.HARPIA_U8, t.uint16: _lib.HARPIA_U16, t.float32: _lib.HARPIA_F32,
+            t.float16: _lib.HARPIA_F16, t.bfloat16: _lib.HARPIA_BF16}
+
+
+_NAMES = {"u8": _lib.HARPIA_U8, "u16": _lib.HARPIA_U16, "f32": _lib.HARPIA_F32,
+          "f16": _lib.HARPIA_F16, "bf16": _lib.HARPIA_BF16}
+
+
+class Exec:
+    """Execution options (harpia_exec): device budget in bytes (0: fraction of
+    free memory), budget fraction, chunk extent {z, y, x} (zeros: z-slabs),
+    flags, and an optional harpia_stats to fill."""
+
+    def __init__(self, budget: int = 0, fraction: float = 0.0, chunk=(0, 0, 0),
+                 force_chunked: bool = False, stats: harpia_stats | None = None):
+        self.budget = budget
+        self.fraction = fraction
+        self.chunk = tuple(chunk)
+        self.force_chunked = force_chunked
+        self.stats = stats
+
+
+def version() -> str:
+    return _lib.load().harpia_version().decode()
+
+
+def gauss_radius(sigma: float, truncate: float = 3.0) -> int:
+    return int(_lib.load().harpia_gauss_radius(float(sigma), float(truncate)))
+
+
+def _is_torch(x) -> bool:
+    try:
+        torch = _torch()
+    except ImportError:  # pragma: no cover
+        return False
+    return isinstance(x, torch.Tensor)
+
+
+def _dtype_code(x) -> int:
+    if _is_torch(x):
+        try:
+            return _torch_dt()[x.dtype]
+        except KeyError:
+            raise HarpiaError(_lib.HARPIA_ERR_DTYPE, "unsupported dtype %s" % x.dtype)
+    try:
+        return _NP_DT[np.asarray(x).dtype]
+    except KeyError:
+        raise HarpiaError(_lib.HARPIA_ERR_DTYPE, "unsupported dtype %s" % np.asarray(x).dtype)
+
+
+def _check_volume(x):
+    if x.ndim != 3:
+        raise ValueError("volumes are 3D [nz, ny, nx]")
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("volume must be contiguous")
+    elif not x.flags["C_CONTIGUOUS"]:
+        raise ValueError("volume must be C-contiguous")
+
+
+def _empty_like(x, code: int):
+    if _is_torch(x):
+        torch = _torch()
+        inv = {v: k for k, v in _torch_dt().items()}
+        return torch.empty(tuple(x.shape), dtype=inv[code], device=x.device,
+                           pin_memory=(x.device.type == "cpu" and x.is_pinned()))
+    if code not in _DT_NP:
+        raise HarpiaError(_lib.HARPIA_ERR_DTYPE, "numpy has no bfloat16")
+    return np.empty(x.shape, dtype=_DT_NP[code])
+
+
+def _ptr(x) -> int:
+    return x.data_ptr() if _is_torch(x) else x.ctypes.data
+
+
+def _exec(x, ex: Exec | None, flags: int = 0):
+    stream = None
+    if _is_torch(x) and x.is_cuda:
+        torch = _torch()
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+    ex = ex or Exec()
+    if ex.force_chunked:
+        flags |= _lib.HARPIA_F_FORCE_CHUNKED
+    return _lib.make_exec(ex.budget, ex.fraction, ex.chunk, stream, flags, ex.stats)
+
+
+def _device_guard(x):
+    if _is_torch(x) and x.is_cuda:
+        return _torch().cuda.device(x.device)
+    import contextlib
+    return contextlib.nullcontext()
+
+
+def _triple(v, cast):
+    if np.ndim(v) == 0:
+        return (cast(v),) * 3
+    v = tuple(cast(t) for t in v)
+    if len(v) != 3:
+        raise ValueError("expected a scalar or a (z, y, x) triple")
+    return v
+
+
+def _code(dt) -> int:
+    if dt is None:
+        return -1
+    if isinstance(dt, str):
+        return _NAMES[dt]
+    if _is_torch_dtype(dt):
+        return _torch_dt()[dt]
+    return _NP_DT[np.dtype(dt)]
+
+
+def _is_torch_dtype(dt) -> bool:
+    try:
+        return isinstance(dt, _torch().dtype)
+    except ImportError:  # pragma: no cover
+        return False
+
+
+def gaussian(x, sigma, truncate: float = 3.0, out=None, out_dtype=None, ex: Exec | None = None):
+    """Gaussian smoothing (reflect boundary, FP64 taps, FP32 accumulation).
+    out dtype: float32 for u8/u16/f32 inputs, the input's dtype for f16/bf16
+    unless out_dtype says float32."""
+    _check_volume(x)
+    ic = _dtype_code(x)
+    oc = _code(out_dtype)
+    if oc < 0:
+        oc = ic if ic in (_lib.HARPIA_F16, _lib.HARPIA_BF16) else _lib.HARPIA_F32
+    if out is None:
+        out = _empty_like(x, oc)
+    else:
+        _check_volume(out)
+        oc = _dtype_code(out)
+    e = _exec(x, ex)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_gaussian3d(
+            _ptr(x), ic, _ptr(out), oc, _lib.i64_3(x.shape), _lib.f64_3(_triple(sigma, float)),
+            float(truncate), _lib.HARPIA_BORDER_REFLECT, e))
+    return out
+
+
+def _morph_prep(x, se, radius, threshold, binary, ex, out):
+    _check_volume(x)
+    ic = _dtype_code(x)
+    se_code = {"box": _lib.HARPIA_SE_BOX, "ball": _lib.HARPIA_SE_BALL}[se]
+    thr = float("nan") if threshold is None else float(threshold)
+    is_bin = binary or threshold is not None
+    oc = _lib.HARPIA_U8 if is_bin else ic
+    flags = _lib.HARPIA_F_BINARY if binary else 0
+    if out is None:
+        out = _empty_like(x, oc)
+    else:
+        _check_volume(out)
+    return ic, se_code, _lib.i32_3(_triple(radius, int)), thr, _exec(x, ex, flags), out, oc
+
+
+def erode(x, se: str = "box", radius=1, threshold=None, binary: bool = False, out=None,
+          ex: Exec | None = None):
+    """Erosion (min over the element).  threshold / binary: binarise the
+    input (v > threshold, or v != 0) and return uint8 {0, 1}."""
+    ic, sc, r, thr, e, out, _ = _morph_prep(x, se, radius, threshold, binary, ex, out)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_erode3d(_ptr(x), _ptr(out), ic, _lib.i64_3(x.shape), sc, r, thr,
+                                              _lib.HARPIA_BORDER_REFLECT, e))
+    return out
+
+
+def dilate(x, se: str = "box", radius=1, threshold=None, binary: bool = False, out=None,
+           ex: Exec | None = None):
+    """Dilation (max over the element); binarisation as in erode()."""
+    ic, sc, r, thr, e, out, _ = _morph_prep(x, se, radius, threshold, binary, ex, out)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_dilate3d(_ptr(x), _ptr(out), ic, _lib.i64_3(x.shape), sc, r, thr,
+                                               _lib.HARPIA_BORDER_REFLECT, e))
+    return out
+
+
+def erode_dilate(x, se: str = "box", radius=1, threshold=None, binary: bool = False,
+                 ex: Exec | None = None):
+    """(erosion, dilation) from one read of the input."""
+    ic, sc, r, thr, e, out, oc = _morph_prep(x, se, radius, threshold, binary, ex, None)
+    out2 = _empty_like(x, oc)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_erode_dilate3d(_ptr(x), _ptr(out), _ptr(out2), ic,
+                                                     _lib.i64_3(x.shape), sc, r, thr,
+                                                     _lib.HARPIA_BORDER_REFLECT, e))
+    return out, out2
+
+
+def morph(x, ops, se: str = "box", radius=1, threshold=None, binary: bool = False, out=None,
+          ex: Exec | None = None):
+    """Chain of 'erode' / 'dilate' steps with one element."""
+    codes = [{"erode": _lib.HARPIA_ERODE, "dilate": _lib.HARPIA_DILATE}[o] for o in ops]
+    ic, sc, r, thr, e, out, _ = _morph_prep(x, se, radius, threshold, binary, ex, out)
+    arr = (ctypes_int * len(codes))(*codes)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_morph3d(_ptr(x), _ptr(out), ic, _lib.i64_3(x.shape), arr,
+                                              len(codes), sc, r, thr, _lib.HARPIA_BORDER_REFLECT, e))
+    return out
+
+
+def opening(x, se: str = "box", radius=1, threshold=None, binary: bool = False, out=None,
+            ex: Exec | None = None):
+    """Opening: dilation of the erosion."""
+    return morph(x, ["erode", "dilate"], se, radius, threshold, binary, out, ex)
+
+
+def closing(x, se: str = "box", radius=1, threshold=None, binary: bool = False, out=None,
+            ex: Exec | None = None):
+    """Closing: erosion of the dilation."""
+    return morph(x, ["dilate", "erode"], se, radius, threshold, binary, out, ex)
+
+
+def plan(shape, in_dtype="f32", out_dtype="f32", halo=(0, 0, 0), budget: int = 0,
+         fraction: float = 0.0, chunk=(0, 0, 0)) -> harpia_plan:
+    """Chunk plan for a streamed volume (harpia_chunk_plan)."""
+    p = harpia_plan()
+    e = _lib.make_exec(budget, fraction, chunk)
+    _lib.check(_lib.load().harpia_chunk_plan(_lib.i64_3(shape), _code(in_dtype), _code(out_dtype),
+                                            _lib.i32_3(_triple(halo, int)), e, p))
+    return p
+
+
+import ctypes as _ctypes  # noqa: E402
+
+ctypes_int = _ctypes.c_int

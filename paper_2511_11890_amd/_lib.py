@@ -1,0 +1,140 @@
+"""ctypes binding of libharpia (include/harpia.h): names, structs and
+signatures mirror the header one to one; this module only marshals
+arguments.  Every filter runs in the HIP library; there is no Python or CPU
+fallback, and loading fails loudly if the library has not been built."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libharpia.so")
+
+# harpia_status
+HARPIA_OK = 0
+HARPIA_ERR_ARG = -1
+HARPIA_ERR_DTYPE = -2
+HARPIA_ERR_BUDGET = -3
+HARPIA_ERR_OOM = -4
+HARPIA_ERR_HIP = -5
+HARPIA_ERR_ALIAS = -6
+HARPIA_ERR_UNSUPPORTED = -7
+STATUS_NAMES = {
+    0: "HARPIA_OK", -1: "HARPIA_ERR_ARG", -2: "HARPIA_ERR_DTYPE", -3: "HARPIA_ERR_BUDGET",
+    -4: "HARPIA_ERR_OOM", -5: "HARPIA_ERR_HIP", -6: "HARPIA_ERR_ALIAS", -7: "HARPIA_ERR_UNSUPPORTED",
+}
+
+# harpia_dtype
+HARPIA_U8, HARPIA_U16, HARPIA_F32, HARPIA_F16, HARPIA_BF16 = 0, 1, 2, 3, 4
+# harpia_se
+HARPIA_SE_BOX, HARPIA_SE_BALL = 0, 1
+# harpia_border
+HARPIA_BORDER_REFLECT = 0
+# harpia_morph_op
+HARPIA_ERODE, HARPIA_DILATE = 0, 1
+# flags
+HARPIA_F_BINARY = 0x1
+HARPIA_F_FORCE_CHUNKED = 0x2
+
+
+class harpia_stats(ctypes.Structure):
+    _fields_ = [("n_chunks", ctypes.c_int64), ("bytes_h2d", ctypes.c_int64),
+                ("bytes_d2h", ctypes.c_int64), ("peak_device_bytes", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_int64), ("wall_ms", ctypes.c_double)]
+
+
+class harpia_exec(ctypes.Structure):
+    _fields_ = [("device_budget_bytes", ctypes.c_size_t), ("budget_fraction", ctypes.c_double),
+                ("chunk", ctypes.c_int64 * 3), ("stream", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32), ("stats", ctypes.POINTER(harpia_stats))]
+
+
+class harpia_plan(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int64 * 3), ("core", ctypes.c_int64 * 3),
+                ("grid", ctypes.c_int64 * 3), ("halo", ctypes.c_int32 * 3),
+                ("n_buffers", ctypes.c_int32), ("n_chunks", ctypes.c_int64),
+                ("device_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t)]
+
+
+class HarpiaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
+        self.status = status
+        self.message = message
+
+
+_I64_3 = ctypes.c_int64 * 3
+_I32_3 = ctypes.c_int32 * 3
+_F64_3 = ctypes.c_double * 3
+_vp = ctypes.c_void_p
+_ex = ctypes.POINTER(harpia_exec)
+
+# name -> (restype, argtypes); the order follows include/harpia.h
+SIGNATURES = {
+    "harpia_last_error": (ctypes.c_char_p, []),
+    "harpia_version": (ctypes.c_char_p, []),
+    "harpia_gauss_radius": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double]),
+    "harpia_chunk_plan": (ctypes.c_int, [_I64_3, ctypes.c_int, ctypes.c_int, _I32_3, _ex,
+                                         ctypes.POINTER(harpia_plan)]),
+    "harpia_gaussian3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _I64_3, _F64_3,
+                                         ctypes.c_double, ctypes.c_int, _ex]),
+    "harpia_erode3d": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _I64_3, ctypes.c_int, _I32_3,
+                                      ctypes.c_double, ctypes.c_int, _ex]),
+    "harpia_dilate3d": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _I64_3, ctypes.c_int, _I32_3,
+                                       ctypes.c_double, ctypes.c_int, _ex]),
+    "harpia_erode_dilate3d": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _I64_3, ctypes.c_int,
+                                             _I32_3, ctypes.c_double, ctypes.c_int, _ex]),
+    "harpia_morph3d": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _I64_3, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.c_int32, ctypes.c_int, _I32_3, ctypes.c_double,
+                                      ctypes.c_int, _ex]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libharpia.so (built by paper_2511_11890_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libharpia.so is not built (%s); run __graft_entry__.build() or "
+                          "python paper_2511_11890_amd/build.py" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    """Raise HarpiaError with the library's message for a failing status."""
+    if status != HARPIA_OK:
+        msg = load().harpia_last_error()
+        raise HarpiaError(status, msg.decode() if msg else "")
+
+
+def i64_3(v):
+    return _I64_3(*[int(t) for t in v])
+
+
+def i32_3(v):
+    return _I32_3(*[int(t) for t in v])
+
+
+def f64_3(v):
+    return _F64_3(*[float(t) for t in v])
+
+
+def make_exec(budget: int = 0, fraction: float = 0.0, chunk=(0, 0, 0), stream: int | None = None,
+              flags: int = 0, stats: harpia_stats | None = None) -> harpia_exec:
+    ex = harpia_exec()
+    ex.device_budget_bytes = int(budget)
+    ex.budget_fraction = float(fraction)
+    ex.chunk = i64_3(chunk)
+    ex.stream = stream
+    ex.flags = int(flags)
+    ex.stats = ctypes.pointer(stats) if stats is not None else None
+    return ex

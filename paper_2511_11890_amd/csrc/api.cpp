@@ -1,0 +1,320 @@
+// C ABI of libharpia (include/harpia.h): argument validation, error
+// reporting and translation of each call into an engine job.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "engine.h"
+
+namespace harpia {
+
+namespace {
+thread_local std::string t_last_error;
+}
+
+void fail(harpia_status st, const std::string &msg) { throw Error{st, msg}; }
+
+void check_hip(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(HARPIA_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+size_t dtype_size(harpia_dtype t)
+{
+    switch (t) {
+    case HARPIA_U8: return 1;
+    case HARPIA_U16: return 2;
+    case HARPIA_F32: return 4;
+    case HARPIA_F16: return 2;
+    case HARPIA_BF16: return 2;
+    }
+    return 0;
+}
+
+const char *dtype_name(harpia_dtype t)
+{
+    switch (t) {
+    case HARPIA_U8: return "u8";
+    case HARPIA_U16: return "u16";
+    case HARPIA_F32: return "f32";
+    case HARPIA_F16: return "f16";
+    case HARPIA_BF16: return "bf16";
+    }
+    return "?";
+}
+
+namespace {
+
+template <class F>
+harpia_status guarded(F &&f)
+{
+    try {
+        f();
+        t_last_error.clear();
+        return HARPIA_OK;
+    } catch (const Error &e) {
+        t_last_error = e.message;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        t_last_error = "host allocation failed";
+        return HARPIA_ERR_OOM;
+    } catch (const std::exception &e) {
+        t_last_error = std::string("internal error: ") + e.what();
+        return HARPIA_ERR_HIP;
+    }
+}
+
+bool valid_dtype(int t) { return t >= HARPIA_U8 && t <= HARPIA_BF16; }
+
+void check_shape(const int64_t *shape)
+{
+    if (!shape) fail(HARPIA_ERR_ARG, "shape is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (shape[a] <= 0) fail(HARPIA_ERR_ARG, "shape extents must be > 0");
+    const double total = (double)shape[0] * (double)shape[1] * (double)shape[2];
+    if (total > 9.0e18) fail(HARPIA_ERR_ARG, "volume too large");
+}
+
+void check_exec(const harpia_exec *ex)
+{
+    if (!ex) return;
+    if (ex->budget_fraction < 0.0 || ex->budget_fraction > 1.0)
+        fail(HARPIA_ERR_ARG, "budget_fraction must be in [0, 1]");
+    for (int a = 0; a < 3; ++a)
+        if (ex->chunk[a] < 0) fail(HARPIA_ERR_ARG, "chunk extents must be >= 0");
+}
+
+void check_alias(const void *in, size_t in_bytes, const void *out, size_t out_bytes)
+{
+    const uintptr_t a0 = (uintptr_t)in, a1 = a0 + in_bytes;
+    const uintptr_t b0 = (uintptr_t)out, b1 = b0 + out_bytes;
+    if (a0 < b1 && b0 < a1) fail(HARPIA_ERR_ALIAS, "input and output overlap");
+}
+
+int64_t voxels(const int64_t *shape) { return shape[0] * shape[1] * shape[2]; }
+
+bool gauss_pair_ok(harpia_dtype i, harpia_dtype o)
+{
+    return (i == HARPIA_F32 && o == HARPIA_F32) || (i == HARPIA_U16 && o == HARPIA_F32) ||
+           (i == HARPIA_U8 && o == HARPIA_F32) || (i == HARPIA_F16 && (o == HARPIA_F16 || o == HARPIA_F32)) ||
+           (i == HARPIA_BF16 && (o == HARPIA_BF16 || o == HARPIA_F32));
+}
+
+Stage gauss_stage(harpia_dtype in_t, harpia_dtype out_t, const double *sigma, double truncate)
+{
+    for (int a = 0; a < 3; ++a)
+        if (!(sigma[a] > 0.0) || !std::isfinite(sigma[a])) fail(HARPIA_ERR_ARG, "sigma must be finite and > 0");
+    if (!(truncate >= 0.0) || !std::isfinite(truncate)) fail(HARPIA_ERR_ARG, "truncate must be finite and >= 0");
+    Stage st;
+    st.kind = Stage::GAUSS;
+    st.in_t = in_t;
+    st.out_t = out_t;
+    int r[3];
+    for (int a = 0; a < 3; ++a) {
+        const double rr = truncate * sigma[a] + 0.5;
+        if (rr >= (double)kMaxGaussRadius + 1.0)
+            fail(HARPIA_ERR_UNSUPPORTED, "Gaussian radius above " + std::to_string(kMaxGaussRadius));
+        r[a] = (int)rr;
+        st.r[a] = r[a];
+    }
+    make_gauss_taps_r(sigma, r, st.taps);
+    return st;
+}
+
+struct MorphArgs {
+    harpia_se se;
+    int r[3];
+    bool binary;
+    bool has_thr;
+    double thr;
+};
+
+MorphArgs check_morph(harpia_dtype t, harpia_se se, const int32_t *radius, double threshold,
+                      harpia_border border, const harpia_exec *ex)
+{
+    if (!valid_dtype(t)) fail(HARPIA_ERR_DTYPE, "unsupported dtype");
+    if (se != HARPIA_SE_BOX && se != HARPIA_SE_BALL) fail(HARPIA_ERR_ARG, "unknown structuring element");
+    if (border != HARPIA_BORDER_REFLECT) fail(HARPIA_ERR_ARG, "only the reflect border is supported");
+    if (!radius) fail(HARPIA_ERR_ARG, "radius is NULL");
+    MorphArgs m;
+    m.se = se;
+    for (int a = 0; a < 3; ++a) {
+        if (radius[a] < 0 || radius[a] > 64) fail(HARPIA_ERR_ARG, "radius must be in [0, 64]");
+        m.r[a] = radius[a];
+    }
+    if (se == HARPIA_SE_BALL && (m.r[0] != m.r[1] || m.r[1] != m.r[2]))
+        fail(HARPIA_ERR_ARG, "the ball element needs equal radii");
+    m.has_thr = !std::isnan(threshold);
+    m.thr = threshold;
+    m.binary = m.has_thr || (ex && (ex->flags & HARPIA_F_BINARY));
+    return m;
+}
+
+Stage morph_stage(harpia_dtype t, const MorphArgs &m, int op, bool first, Stage::Kind kind)
+{
+    Stage st;
+    st.kind = kind;
+    st.in_t = (first || !m.binary) ? t : HARPIA_U8;
+    st.out_t = m.binary ? HARPIA_U8 : t;
+    for (int a = 0; a < 3; ++a) st.r[a] = m.r[a];
+    st.morph.op = op;
+    st.morph.se = m.se;
+    for (int a = 0; a < 3; ++a) st.morph.r[a] = m.r[a];
+    st.morph.binary = m.binary;
+    // Later steps of a binary chain read u8 {0, 1}: binarise as v != 0.
+    st.morph.has_threshold = first && m.has_thr;
+    st.morph.threshold = m.thr;
+    return st;
+}
+
+}  // namespace
+}  // namespace harpia
+
+using namespace harpia;
+
+extern "C" {
+
+const char *harpia_last_error(void) { return t_last_error.c_str(); }
+
+const char *harpia_version(void) { return "harpia 0.1.0 gfx950"; }
+
+int32_t harpia_gauss_radius(double sigma, double truncate)
+{
+    if (!(sigma > 0.0) || !(truncate >= 0.0) || !std::isfinite(sigma) || !std::isfinite(truncate)) return -1;
+    const double r = truncate * sigma + 0.5;
+    if (r > 2.0e9) return -1;
+    return (int32_t)r;
+}
+
+harpia_status harpia_chunk_plan(const int64_t shape[3], harpia_dtype in_t, harpia_dtype out_t,
+                                const int32_t halo[3], const harpia_exec *ex, harpia_plan *out)
+{
+    return guarded([&] {
+        check_shape(shape);
+        check_exec(ex);
+        if (!out) fail(HARPIA_ERR_ARG, "out is NULL");
+        if (!halo) fail(HARPIA_ERR_ARG, "halo is NULL");
+        if (!valid_dtype(in_t) || !valid_dtype(out_t)) fail(HARPIA_ERR_DTYPE, "unsupported dtype");
+        for (int a = 0; a < 3; ++a)
+            if (halo[a] < 0) fail(HARPIA_ERR_ARG, "halo must be >= 0");
+        // A single stencil step with the given halo, staged from the host.
+        Stage st;
+        std::memset(&st, 0, sizeof(st));
+        st.kind = Stage::MORPH;
+        st.in_t = in_t;
+        st.out_t = out_t;
+        for (int a = 0; a < 3; ++a) st.r[a] = halo[a];
+        std::vector<Stage> stages{st};
+        ChunkCost cost{true, dtype_size(in_t), dtype_size(out_t), 1, &stages};
+        const size_t budget = resolve_budget(ex, true);
+        const int64_t zero[3] = {0, 0, 0};
+        plan_chunks(shape, halo, ex ? ex->chunk : zero, cost, budget, 3, *out);
+    });
+}
+
+harpia_status harpia_gaussian3d(const void *in, harpia_dtype in_t, void *out, harpia_dtype out_t,
+                                const int64_t shape[3], const double sigma[3], double truncate,
+                                harpia_border border, const harpia_exec *ex)
+{
+    return guarded([&] {
+        if (!in || !out) fail(HARPIA_ERR_ARG, "in / out is NULL");
+        check_shape(shape);
+        check_exec(ex);
+        if (!sigma) fail(HARPIA_ERR_ARG, "sigma is NULL");
+        if (border != HARPIA_BORDER_REFLECT) fail(HARPIA_ERR_ARG, "only the reflect border is supported");
+        if (!valid_dtype(in_t) || !valid_dtype(out_t)) fail(HARPIA_ERR_DTYPE, "unsupported dtype");
+        if (!gauss_pair_ok(in_t, out_t))
+            fail(HARPIA_ERR_DTYPE, std::string("unsupported Gaussian dtype pair ") + dtype_name(in_t) + " -> " +
+                                       dtype_name(out_t));
+        const int64_t nv = voxels(shape);
+        check_alias(in, nv * dtype_size(in_t), out, nv * dtype_size(out_t));
+        Job job;
+        job.in = in;
+        job.out = out;
+        job.out2 = nullptr;
+        for (int a = 0; a < 3; ++a) job.n[a] = shape[a];
+        job.stages.push_back(gauss_stage(in_t, out_t, sigma, truncate));
+        job.ex = ex;
+        run_job(job);
+    });
+}
+
+static harpia_status morph_common(const void *in, void *out, harpia_dtype t, const int64_t shape[3],
+                                  const harpia_morph_op *ops, int32_t n_ops, harpia_se se,
+                                  const int32_t radius[3], double threshold, harpia_border border,
+                                  const harpia_exec *ex)
+{
+    return guarded([&] {
+        if (!in || !out) fail(HARPIA_ERR_ARG, "in / out is NULL");
+        check_shape(shape);
+        check_exec(ex);
+        if (!ops || n_ops < 1 || n_ops > 8) fail(HARPIA_ERR_ARG, "n_ops must be in [1, 8]");
+        for (int i = 0; i < n_ops; ++i)
+            if (ops[i] != HARPIA_ERODE && ops[i] != HARPIA_DILATE) fail(HARPIA_ERR_ARG, "unknown morphology op");
+        const MorphArgs m = check_morph(t, se, radius, threshold, border, ex);
+        const int64_t nv = voxels(shape);
+        const harpia_dtype out_t = m.binary ? HARPIA_U8 : t;
+        check_alias(in, nv * dtype_size(t), out, nv * dtype_size(out_t));
+        Job job;
+        job.in = in;
+        job.out = out;
+        job.out2 = nullptr;
+        for (int a = 0; a < 3; ++a) job.n[a] = shape[a];
+        for (int i = 0; i < n_ops; ++i) job.stages.push_back(morph_stage(t, m, (int)ops[i], i == 0, Stage::MORPH));
+        job.ex = ex;
+        run_job(job);
+    });
+}
+
+harpia_status harpia_erode3d(const void *in, void *out, harpia_dtype t, const int64_t shape[3], harpia_se se,
+                             const int32_t radius[3], double threshold, harpia_border border,
+                             const harpia_exec *ex)
+{
+    const harpia_morph_op op = HARPIA_ERODE;
+    return morph_common(in, out, t, shape, &op, 1, se, radius, threshold, border, ex);
+}
+
+harpia_status harpia_dilate3d(const void *in, void *out, harpia_dtype t, const int64_t shape[3], harpia_se se,
+                              const int32_t radius[3], double threshold, harpia_border border,
+                              const harpia_exec *ex)
+{
+    const harpia_morph_op op = HARPIA_DILATE;
+    return morph_common(in, out, t, shape, &op, 1, se, radius, threshold, border, ex);
+}
+
+harpia_status harpia_morph3d(const void *in, void *out, harpia_dtype t, const int64_t shape[3],
+                             const harpia_morph_op *ops, int32_t n_ops, harpia_se se, const int32_t radius[3],
+                             double threshold, harpia_border border, const harpia_exec *ex)
+{
+    return morph_common(in, out, t, shape, ops, n_ops, se, radius, threshold, border, ex);
+}
+
+harpia_status harpia_erode_dilate3d(const void *in, void *out_erode, void *out_dilate, harpia_dtype t,
+                                    const int64_t shape[3], harpia_se se, const int32_t radius[3],
+                                    double threshold, harpia_border border, const harpia_exec *ex)
+{
+    return guarded([&] {
+        if (!in || !out_erode || !out_dilate) fail(HARPIA_ERR_ARG, "in / out is NULL");
+        check_shape(shape);
+        check_exec(ex);
+        const MorphArgs m = check_morph(t, se, radius, threshold, border, ex);
+        const int64_t nv = voxels(shape);
+        const harpia_dtype out_t = m.binary ? HARPIA_U8 : t;
+        check_alias(in, nv * dtype_size(t), out_erode, nv * dtype_size(out_t));
+        check_alias(in, nv * dtype_size(t), out_dilate, nv * dtype_size(out_t));
+        check_alias(out_erode, nv * dtype_size(out_t), out_dilate, nv * dtype_size(out_t));
+        Job job;
+        job.in = in;
+        job.out = out_erode;
+        job.out2 = out_dilate;
+        for (int a = 0; a < 3; ++a) job.n[a] = shape[a];
+        job.stages.push_back(morph_stage(t, m, HARPIA_ERODE, true, Stage::MORPH_BOTH));
+        job.ex = ex;
+        run_job(job);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// Internal definitions shared by the HIP kernels and the host engine of
+// libharpia.  Not part of the public ABI (that is include/harpia.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "harpia.h"
+
+namespace harpia {
+
+// ----------------------------------------------------------------- errors
+
+struct Error {
+    harpia_status status;
+    std::string message;
+};
+
+[[noreturn]] void fail(harpia_status st, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+
+// ----------------------------------------------------------------- dtypes
+
+struct bf16_t {
+    uint16_t bits;
+};
+
+size_t dtype_size(harpia_dtype t);
+const char *dtype_name(harpia_dtype t);
+
+// Element conversions used inside kernels.  Every storage type converts to
+// float exactly (u8, u16, f16 and bf16 values are all representable).
+__device__ __forceinline__ float to_f32(uint8_t v) { return (float)v; }
+__device__ __forceinline__ float to_f32(uint16_t v) { return (float)v; }
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(_Float16 v) { return (float)v; }
+__device__ __forceinline__ float to_f32(bf16_t v)
+{
+    return __uint_as_float(((uint32_t)v.bits) << 16);
+}
+
+template <typename T> __device__ __forceinline__ T from_f32(float v);
+template <> __device__ __forceinline__ float from_f32<float>(float v) { return v; }
+template <> __device__ __forceinline__ _Float16 from_f32<_Float16>(float v)
+{
+    return (_Float16)v;  // round to nearest even
+}
+// Round to nearest even: add 0x7fff plus the lowest kept bit, truncate.
+// NaN keeps its sign and becomes a quiet NaN.
+template <> __device__ __forceinline__ bf16_t from_f32<bf16_t>(float v)
+{
+    uint32_t u = __float_as_uint(v);
+    bf16_t r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+        r.bits = (uint16_t)((u >> 16) | 0x0040u);
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);
+        r.bits = (uint16_t)(u >> 16);
+    }
+    return r;
+}
+// Morphology outputs are input values, so these conversions are exact.
+template <> __device__ __forceinline__ uint16_t from_f32<uint16_t>(float v)
+{
+    return (uint16_t)v;
+}
+template <> __device__ __forceinline__ uint8_t from_f32<uint8_t>(float v)
+{
+    return (uint8_t)v;
+}
+
+// ------------------------------------------------------------ reflection
+
+// Half-sample symmetric reflection of i into [0, n), valid for any i.
+__host__ __device__ __forceinline__ int64_t reflect_index(int64_t i, int64_t n)
+{
+    if (i >= 0 && i < n) return i;
+    int64_t p = 2 * n;
+    int64_t m = i % p;
+    if (m < 0) m += p;
+    return m < n ? m : p - 1 - m;
+}
+
+// --------------------------------------------------------------- regions
+
+// A box-shaped region of a volume stored densely in device memory:
+// element (z, y, x) of the region (global coordinates o + (z, y, x)) lives at
+// ptr + z * sz + y * sy + x (element units).
+struct Region {
+    void *ptr;
+    int64_t sy, sz;
+    int64_t o[3];  // global origin {z, y, x}
+    int64_t e[3];  // extent
+};
+
+// Kernel-side description of one filter application on a chunk: read from
+// `in` (which covers every reflected index the output region needs), write
+// the output region `out`.  n[] is the global volume extent.
+struct ChunkArgs {
+    const void *in;
+    int64_t in_sy, in_sz;
+    int64_t in_o[3];
+    void *out;
+    int64_t out_sy, out_sz;
+    int64_t out_o[3];
+    int64_t out_e[3];
+    int64_t n[3];
+};
+
+inline ChunkArgs make_chunk_args(const Region &in, const Region &out, const int64_t n[3])
+{
+    ChunkArgs a;
+    a.in = in.ptr;
+    a.in_sy = in.sy;
+    a.in_sz = in.sz;
+    a.out = out.ptr;
+    a.out_sy = out.sy;
+    a.out_sz = out.sz;
+    for (int i = 0; i < 3; ++i) {
+        a.in_o[i] = in.o[i];
+        a.out_o[i] = out.o[i];
+        a.out_e[i] = out.e[i];
+        a.n[i] = n[i];
+    }
+    return a;
+}
+
+// Map a linear block index so that the blocks one XCD runs (the hardware
+// deals consecutive workgroups round-robin over the 8 XCDs) cover a
+// contiguous range of tiles, which then share halos in that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb)
+{
+    constexpr uint32_t kXcd = 8;
+    uint32_t full = nb - nb % kXcd;
+    if (b >= full) return b;
+    return (b % kXcd) * (full / kXcd) + b / kXcd;
+}
+
+// ------------------------------------------------------------ launchers
+
+constexpr int kMaxGaussRadius = 64;  // unfused-path limit per axis
+constexpr int kGaussFusedMaxR = 12;  // fused z-streaming kernel: 1 <= r <= this
+
+struct GaussTaps {
+    int r[3];                                 // radius per axis {z, y, x}
+    float w[3][kMaxGaussRadius + 1];          // half taps w[a][|k|], FP32
+};
+
+// Fills taps in FP64 and rounds them to FP32 (host).
+void make_gauss_taps(const double sigma[3], double truncate, GaussTaps &t);
+void make_gauss_taps_r(const double sigma[3], const int radius[3], GaussTaps &t);
+
+// Launch the Gaussian on one chunk.  Returns false if no kernel handles the
+// dtype pair / radius combination (caller reports UNSUPPORTED).
+bool launch_gaussian(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t,
+                     const GaussTaps &taps, hipStream_t s, void *scratch,
+                     size_t scratch_bytes);
+// Scratch bytes the Gaussian needs for an output region of `out_e` voxels
+// (0 for the fused kernel).
+size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3]);
+
+struct MorphSpec {
+    int op;              // 0 erode (min), 1 dilate (max)
+    int se;              // harpia_se
+    int r[3];            // radius per axis
+    bool binary;         // binarise on load, u8 output
+    bool has_threshold;  // binary: compare with threshold; else v != 0
+    double threshold;
+};
+
+bool launch_morph(const ChunkArgs &a, harpia_dtype t, const MorphSpec &m, hipStream_t s);
+// With both = true the step writes the erosion to a.out and the dilation to
+// *out2 from one read of the input.
+bool launch_morph_ex(const ChunkArgs &a, harpia_dtype t, const MorphSpec &m, bool both, const Region *out2,
+                     hipStream_t s);
+float compare_threshold(harpia_dtype t, double thr);
+
+}  // namespace harpia

@@ -1,0 +1,56 @@
+// Chunked execution engine (Section III-D of the paper: query free device
+// memory, reserve a fixed fraction of it, size the chunks so each fits with
+// its padding, run the chunks independently on one GPU).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace harpia {
+
+// One filter step of a pipeline.
+struct Stage {
+    enum Kind { GAUSS, MORPH, MORPH_BOTH } kind;
+    harpia_dtype in_t, out_t;  // element types read and written by the step
+    int r[3];                  // radius per axis (the halo this step needs)
+    GaussTaps taps;            // GAUSS
+    MorphSpec morph;           // MORPH / MORPH_BOTH
+};
+
+struct Job {
+    const void *in;
+    void *out;
+    void *out2;  // second output of MORPH_BOTH (same dtype as out)
+    int64_t n[3];
+    std::vector<Stage> stages;
+    const harpia_exec *ex;
+};
+
+// Byte cost of one chunk's buffer set, for the planner.
+struct ChunkCost {
+    bool host;              // staging buffers for host-resident volumes
+    size_t in_es, out_es;   // element sizes of the staged input / output
+    int n_out;              // outputs per voxel (2 for MORPH_BOTH)
+    const std::vector<Stage> *stages;
+};
+
+size_t chunk_bytes(const ChunkCost &c, const int64_t core[3], const int64_t n[3]);
+
+// Plan the tiling of n[] into cores with halo[] per side within `budget`
+// bytes (Section III-D, step 2).  chunk[] = {0,0,0} picks z-slabs: the
+// deepest slab (full y and x) that fits, capped so that large volumes give
+// several chunks to overlap transfers with compute.  Throws on failure.
+void plan_chunks(const int64_t n[3], const int32_t halo[3], const int64_t chunk[3], const ChunkCost &cost,
+                 size_t budget, int max_buffers, harpia_plan &p);
+
+// Device budget in bytes: explicit cap, else fraction x free device memory
+// (Section III-D, step 1).  Environment overrides: HARPIA_DEVICE_BUDGET
+// (bytes), HARPIA_BUDGET_FRACTION.
+size_t resolve_budget(const harpia_exec *ex, bool need_device);
+
+// Run a job: resident on the caller's stream when `in`/`out` are device
+// pointers, streamed chunk by chunk when they are host pointers.
+void run_job(const Job &job);
+
+}  // namespace harpia

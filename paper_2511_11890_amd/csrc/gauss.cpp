@@ -1,0 +1,82 @@
+// Gaussian smoothing kernels for gfx950 (the Gaussian filter of the
+// library's filtering suite, Section III-C).
+//
+// out[z,y,x] = sum_{a,b,c} wz[a] wy[b] wx[c] in[R(z+a), R(y+b), R(x+c)]
+// with half-sample reflection R and normalised sampled taps (FP64 -> FP32).
+//
+// Fused kernel (equal radius r on all axes, 1 <= r <= kGaussFusedMaxR):
+//   one 256-thread workgroup owns a kTX x kTY tile of output columns and
+//   streams along z over a range of output slices.  Per input slice it
+//     1. stages the (kTX+2r) x (kTY+2r) patch in LDS (reflection applied on
+//        load, converted to f32) -- the global loads of the next slice are
+//        issued before the current slice is filtered, so HBM latency hides
+//        behind the LDS work;
+//     2. y pass from LDS, register-blocked kMY rows per work item;
+//     3. x pass from LDS, 4 adjacent columns per thread (b128 LDS reads);
+//     4. z pass in registers: each thread keeps a ring of 2r+1 partial sums
+//        for each of its 4 columns; slice s adds w|s-o| * t to output o for
+//        o in [s-r, s+r], and output s-r is then complete and stored.
+//   HBM traffic is one read of the input and one write of the output per
+//   voxel (halo re-reads hit L2: xcd_remap keeps neighbouring tiles on one
+//   XCD).  The ring is indexed statically by unrolling the slice loop 2r+1
+//   times.
+//
+// Unfused kernels (any radius up to kMaxGaussRadius, anisotropic radii):
+//   three 1D passes through FP32 scratch, one thread per output voxel.
+#include <cmath>
+
+#include "common.h"
+
+namespace harpia {
+
+template <typename Tin, typename Tout>
+bool gauss_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes);
+
+size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3])
+{
+    if (r[0] == r[1] && r[1] == r[2] && r[0] >= 1 && r[0] <= kGaussFusedMaxR) return 0;
+    // worst case input region: output extent + 2r per axis
+    const int64_t iz = out_e[0] + 2 * r[0], iy = out_e[1] + 2 * r[1];
+    return (size_t)((iz * iy * out_e[2] + iz * out_e[1] * out_e[2]) * (int64_t)sizeof(float));
+}
+
+void make_gauss_taps_r(const double sigma[3], const int radius[3], GaussTaps &t)
+{
+    for (int ax = 0; ax < 3; ++ax) {
+        const int r = radius[ax];
+        t.r[ax] = r;
+        double e[kMaxGaussRadius + 1];
+        double total = 0.0;
+        for (int k = 0; k <= r; ++k) {
+            e[k] = std::exp(-((double)k * (double)k) / (2.0 * sigma[ax] * sigma[ax]));
+            total += (k == 0) ? e[k] : 2.0 * e[k];
+        }
+        for (int k = 0; k <= kMaxGaussRadius; ++k) t.w[ax][k] = (k <= r) ? (float)(e[k] / total) : 0.f;
+    }
+}
+
+void make_gauss_taps(const double sigma[3], double truncate, GaussTaps &t)
+{
+    int r[3];
+    for (int ax = 0; ax < 3; ++ax) r[ax] = (int)(truncate * sigma[ax] + 0.5);
+    make_gauss_taps_r(sigma, r, t);
+}
+
+bool launch_gaussian(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t, const GaussTaps &taps,
+                     hipStream_t s, void *scratch, size_t scratch_bytes)
+{
+    if (a.out_e[0] <= 0 || a.out_e[1] <= 0 || a.out_e[2] <= 0) return true;
+#define HARPIA_PAIR(IT, OT, TI, TO) \
+    if (in_t == IT && out_t == OT) return gauss_run<TI, TO>(a, taps, s, scratch, scratch_bytes);
+    HARPIA_PAIR(HARPIA_F32, HARPIA_F32, float, float)
+    HARPIA_PAIR(HARPIA_U16, HARPIA_F32, uint16_t, float)
+    HARPIA_PAIR(HARPIA_U8, HARPIA_F32, uint8_t, float)
+    HARPIA_PAIR(HARPIA_F16, HARPIA_F16, _Float16, _Float16)
+    HARPIA_PAIR(HARPIA_F16, HARPIA_F32, _Float16, float)
+    HARPIA_PAIR(HARPIA_BF16, HARPIA_BF16, bf16_t, bf16_t)
+    HARPIA_PAIR(HARPIA_BF16, HARPIA_F32, bf16_t, float)
+#undef HARPIA_PAIR
+    return false;
+}
+
+}  // namespace harpia

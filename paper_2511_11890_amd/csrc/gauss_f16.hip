@@ -1,0 +1,6 @@
+// Gaussian kernels instantiated for _Float16 -> _Float16.
+#include "gauss_impl.h"
+
+namespace harpia {
+template bool gauss_run<_Float16, _Float16>(const ChunkArgs &, const GaussTaps &, hipStream_t, void *, size_t);
+}  // namespace harpia

@@ -1,0 +1,6 @@
+// Gaussian kernels instantiated for float -> float.
+#include "gauss_impl.h"
+
+namespace harpia {
+template bool gauss_run<float, float>(const ChunkArgs &, const GaussTaps &, hipStream_t, void *, size_t);
+}  // namespace harpia

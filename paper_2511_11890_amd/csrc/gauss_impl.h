@@ -1,0 +1,388 @@
+// Gaussian smoothing kernels for gfx950 (templates; instantiated per dtype
+// pair in gauss_<pair>.hip so the build compiles them in parallel) (the Gaussian filter of the
+// library's filtering suite, Section III-C).
+//
+// out[z,y,x] = sum_{a,b,c} wz[a] wy[b] wx[c] in[R(z+a), R(y+b), R(x+c)]
+// with half-sample reflection R and normalised sampled taps (FP64 -> FP32).
+//
+// Fused kernel (equal radius r on all axes, 1 <= r <= kGaussFusedMaxR):
+//   one 256-thread workgroup owns a kTX x kTY tile of output columns and
+//   streams along z over a range of output slices.  Per input slice it
+//     1. stages the (kTX+2r) x (kTY+2r) patch in LDS (reflection applied on
+//        load, converted to f32) -- the global loads of the next slice are
+//        issued before the current slice is filtered, so HBM latency hides
+//        behind the LDS work;
+//     2. y pass from LDS, register-blocked kMY rows per work item;
+//     3. x pass from LDS, 4 adjacent columns per thread (b128 LDS reads);
+//     4. z pass in registers: each thread keeps a ring of 2r+1 partial sums
+//        for each of its 4 columns; slice s adds w|s-o| * t to output o for
+//        o in [s-r, s+r], and output s-r is then complete and stored.
+//   HBM traffic is one read of the input and one write of the output per
+//   voxel (halo re-reads hit L2: xcd_remap keeps neighbouring tiles on one
+//   XCD).  The ring is indexed statically by unrolling the slice loop 2r+1
+//   times.
+//
+// Unfused kernels (any radius up to kMaxGaussRadius, anisotropic radii):
+//   three 1D passes through FP32 scratch, one thread per output voxel.
+#pragma once
+
+#include <cstdint>
+#include <utility>
+
+#include "common.h"
+
+namespace harpia {
+
+// Calls f(std::integral_constant<int, I>) for I = 0..N-1 with I a
+// compile-time constant, so register arrays indexed by I stay in registers.
+template <int... I, class F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, F &&f)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(std::make_integer_sequence<int, N>{}, static_cast<F &&>(f));
+}
+
+namespace gauss_detail {
+
+
+constexpr int kTX = 64;   // tile columns (x)
+constexpr int kTY = 16;   // tile rows (y)
+constexpr int kNT = 256;  // threads per workgroup
+constexpr int kMY = 4;    // rows per y-pass work item
+
+
+static_assert(kTX / 4 * kTY == kNT, "x pass maps one 4-column quad per thread");
+
+template <typename T>
+__device__ __forceinline__ void store4(T *p, const float v[4], int nvalid)
+{
+    if (nvalid >= 4) {
+        if constexpr (sizeof(T) == 4) {
+            if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+                float4 q = make_float4(v[0], v[1], v[2], v[3]);
+                *reinterpret_cast<float4 *>(p) = q;
+                return;
+            }
+        } else if constexpr (sizeof(T) == 2) {
+            if ((reinterpret_cast<uintptr_t>(p) & 7) == 0) {
+                uint16_t h[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    T t = from_f32<T>(v[c]);
+                    h[c] = *reinterpret_cast<uint16_t *>(&t);
+                }
+                uint2 q = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                     (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+                *reinterpret_cast<uint2 *>(p) = q;
+                return;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        if (c < nvalid) p[c] = from_f32<T>(v[c]);
+}
+
+template <typename Tin, typename Tout, int R>
+__global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps taps, int zlen,
+                                                          int tiles_x, int tiles_y)
+{
+    constexpr int P = 2 * R + 1;
+    constexpr int PW = kTX + 2 * R;  // patch columns
+    constexpr int PH = kTY + 2 * R;  // patch rows
+    constexpr int PSZ = PW * PH;
+    constexpr int NLD = (PSZ + kNT - 1) / kNT;
+    constexpr int QP = (PW + 3) & ~3;  // y-pass output pitch, 16-byte rows
+    constexpr int NYI = PW * (kTY / kMY);
+    constexpr int NH = 4 + 2 * R;  // x-pass inputs per quad
+    constexpr int NH4 = (NH + 3) / 4;
+
+    __shared__ float sP[PSZ];
+    __shared__ __attribute__((aligned(16))) float sQ[kTY * QP + 4 * NH4];
+
+    const int tid = threadIdx.x;
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = (int)(b % (uint32_t)tiles_x);
+    const int by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
+    const int bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
+
+    const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
+    const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1];
+    const int64_t x0 = xbeg + (int64_t)bx * kTX;
+    const int64_t y0 = ybeg + (int64_t)by * kTY;
+    const int64_t zo0 = a.out_o[0] + (int64_t)bz * zlen;
+    const int64_t zo1 = min(zo0 + (int64_t)zlen, a.out_o[0] + a.out_e[0]);
+    if (zo0 >= zo1) return;
+
+    float wz[R + 1], wy[R + 1], wx[R + 1];
+#pragma unroll
+    for (int k = 0; k <= R; ++k) {
+        wz[k] = taps.w[0][k];
+        wy[k] = taps.w[1][k];
+        wx[k] = taps.w[2][k];
+    }
+
+    // In-plane source offsets of this thread's patch elements; the same for
+    // every slice.  Coordinates past the output region are clamped (they
+    // only feed outputs that are never stored), so every reflected index
+    // stays inside the input region.
+    int32_t off[NLD];
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+        const int e = tid + i * kNT;
+        off[i] = 0;
+        if (e < PSZ) {
+            const int row = e / PW, col = e - (e / PW) * PW;
+            int64_t gy = y0 - R + row;
+            gy = gy < ybeg - R ? ybeg - R : (gy > yend - 1 + R ? yend - 1 + R : gy);
+            int64_t gx = x0 - R + col;
+            gx = gx < xbeg - R ? xbeg - R : (gx > xend - 1 + R ? xend - 1 + R : gx);
+            const int64_t ly = reflect_index(gy, a.n[1]) - a.in_o[1];
+            const int64_t lx = reflect_index(gx, a.n[2]) - a.in_o[2];
+            off[i] = (int32_t)(ly * a.in_sy + lx);
+        }
+    }
+
+    const Tin *in = static_cast<const Tin *>(a.in);
+    float pf[NLD];
+    auto fetch = [&](int64_t s) __attribute__((always_inline)) {
+        const int64_t zl = reflect_index(s, a.n[0]) - a.in_o[0];
+        const Tin *base = in + zl * a.in_sz;
+#pragma unroll
+        for (int i = 0; i < NLD; ++i)
+            if (i < NLD - 1 || tid + i * kNT < PSZ) pf[i] = to_f32(base[off[i]]);
+    };
+
+    const int qrow = tid / (kTX / 4);
+    const int qcol = (tid % (kTX / 4)) * 4;
+    const int64_t gy_out = y0 + qrow;
+    const int64_t gx_out = x0 + qcol;
+    const int nvalid = (gy_out < yend) ? (int)min((int64_t)4, xend - gx_out) : 0;
+    Tout *outp = static_cast<Tout *>(a.out) + (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
+
+    float acc[P][4];
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[j][c] = 0.f;
+
+    const int64_t s0 = zo0 - R;
+    const int nsteps = (int)(zo1 - zo0) + 2 * R;
+    fetch(s0);
+
+    for (int base = 0; base < nsteps; base += P) {
+        static_for<P>([&](auto U) {
+            constexpr int u = decltype(U)::value;
+            const int i = base + u;
+            if (i >= nsteps) return;
+
+            // 1. stage the slice, then start fetching the next one
+#pragma unroll
+            for (int k = 0; k < NLD; ++k)
+                if (k < NLD - 1 || tid + k * kNT < PSZ) sP[tid + k * kNT] = pf[k];
+            if (i + 1 < nsteps) fetch(s0 + i + 1);
+            __syncthreads();
+
+            // 2. y pass: sP (PH x PW) -> sQ (kTY x PW)
+            for (int it = tid; it < NYI; it += kNT) {
+                const int col = it % PW, rg = it / PW;
+                float v[kMY + 2 * R];
+#pragma unroll
+                for (int j = 0; j < kMY + 2 * R; ++j) v[j] = sP[(rg * kMY + j) * PW + col];
+#pragma unroll
+                for (int m = 0; m < kMY; ++m) {
+                    float sacc = wy[0] * v[m + R];
+#pragma unroll
+                    for (int k = 1; k <= R; ++k) sacc = fmaf(wy[k], v[m + R - k] + v[m + R + k], sacc);
+                    sQ[(rg * kMY + m) * QP + col] = sacc;
+                }
+            }
+            __syncthreads();
+
+            // 3. x pass: 4 adjacent outputs from sQ row qrow
+            float h[NH4 * 4];
+            const float4 *q4 = reinterpret_cast<const float4 *>(&sQ[qrow * QP + qcol]);
+#pragma unroll
+            for (int j = 0; j < NH4; ++j) {
+                const float4 t4 = q4[j];
+                h[4 * j + 0] = t4.x;
+                h[4 * j + 1] = t4.y;
+                h[4 * j + 2] = t4.z;
+                h[4 * j + 3] = t4.w;
+            }
+            float t[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                float sacc = wx[0] * h[c + R];
+#pragma unroll
+                for (int k = 1; k <= R; ++k) sacc = fmaf(wx[k], h[c + R - k] + h[c + R + k], sacc);
+                t[c] = sacc;
+            }
+
+            // 4. z pass: scatter into the ring; slot of output o is (o - s0) mod P
+            static_for<P>([&](auto D) {
+                constexpr int d = decltype(D)::value - R;
+                constexpr int sl = (u + d + 2 * P) % P;
+                const float wd = wz[d < 0 ? -d : d];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[sl][c] = (d == R) ? wd * t[c] : fmaf(wd, t[c], acc[sl][c]);
+            });
+            if (i >= 2 * R) {
+                constexpr int sl = (u - R + 2 * P) % P;
+                const int64_t o = s0 + i - R;
+                if (nvalid > 0) store4(outp + (o - a.out_o[0]) * a.out_sz, acc[sl], nvalid);
+            }
+        });
+    }
+}
+
+// One 1D pass along `axis` (0 z, 1 y, 2 x): dst = w * src, reflect along the
+// axis.  src covers every reflected index; dst is dense or strided.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void gauss_pass_kernel(const Tin *src, int64_t s_sy, int64_t s_sz,
+                                                         int64_t s_oz, int64_t s_oy, int64_t s_ox,
+                                                         Tout *dst, int64_t d_sy, int64_t d_sz,
+                                                         int64_t d_oz, int64_t d_oy, int64_t d_ox,
+                                                         int64_t ez, int64_t ey, int64_t ex,
+                                                         int axis, int64_t n_axis, GaussTaps taps)
+{
+    const int64_t total = ez * ey * ex;
+    const int r = taps.r[axis];
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = id % ex, y = (id / ex) % ey, z = id / (ex * ey);
+        const int64_t g[3] = {d_oz + z, d_oy + y, d_ox + x};
+        float sacc = 0.f;
+        for (int k = -r; k <= r; ++k) {
+            int64_t c[3] = {g[0], g[1], g[2]};
+            c[axis] = reflect_index(g[axis] + k, n_axis);
+            const int64_t off = (c[0] - s_oz) * s_sz + (c[1] - s_oy) * s_sy + (c[2] - s_ox);
+            sacc = fmaf(taps.w[axis][k < 0 ? -k : k], to_f32(src[off]), sacc);
+        }
+        dst[z * d_sz + y * d_sy + x] = from_f32<Tout>(sacc);
+    }
+}
+
+template <typename Tin, typename Tout, int R>
+void launch_fused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
+{
+    const int tiles_x = (int)((a.out_e[2] + kTX - 1) / kTX);
+    const int tiles_y = (int)((a.out_e[1] + kTY - 1) / kTY);
+    const int64_t tiles = (int64_t)tiles_x * tiles_y;
+    // z range per workgroup: enough workgroups to fill the chip several
+    // times over, but long enough that the 2r-slice warm-up stays small.
+    int64_t zlen = a.out_e[0];
+    const int64_t want_blocks = 4096;
+    if (tiles * 1 < want_blocks) {
+        int64_t nzc = (want_blocks + tiles - 1) / tiles;
+        zlen = (a.out_e[0] + nzc - 1) / nzc;
+        const int64_t min_len = 8 * R > 32 ? 8 * R : 32;
+        if (zlen < min_len) zlen = min_len;
+    } else {
+        const int64_t max_len = 256;
+        if (zlen > max_len && tiles < 4 * want_blocks) zlen = max_len;
+    }
+    if (zlen > a.out_e[0]) zlen = a.out_e[0];
+    const int64_t zch = (a.out_e[0] + zlen - 1) / zlen;
+    const int64_t nb = tiles * zch;
+    hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R>), dim3((uint32_t)nb), dim3(kNT), 0, s, a, taps,
+                       (int)zlen, tiles_x, tiles_y);
+}
+
+template <typename Tin, typename Tout>
+bool dispatch_fused(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
+{
+    switch (r) {
+#define HARPIA_CASE(RR)                              \
+    case RR:                                         \
+        launch_fused<Tin, Tout, RR>(a, taps, s);     \
+        return true;
+        HARPIA_CASE(1)
+        HARPIA_CASE(2)
+        HARPIA_CASE(3)
+        HARPIA_CASE(4)
+        HARPIA_CASE(5)
+        HARPIA_CASE(6)
+        HARPIA_CASE(7)
+        HARPIA_CASE(8)
+        HARPIA_CASE(9)
+        HARPIA_CASE(10)
+        HARPIA_CASE(11)
+        HARPIA_CASE(12)
+#undef HARPIA_CASE
+    default:
+        return false;
+    }
+}
+
+template <typename Tin, typename Tout>
+void launch_pass(const Tin *src, const Region &sr, Tout *dst, const Region &dr, int axis,
+                 int64_t n_axis, const GaussTaps &taps, hipStream_t s)
+{
+    const int64_t total = dr.e[0] * dr.e[1] * dr.e[2];
+    if (total == 0) return;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((gauss_pass_kernel<Tin, Tout>), dim3((uint32_t)blocks), dim3(256), 0, s, src, sr.sy,
+                       sr.sz, sr.o[0], sr.o[1], sr.o[2], dst, dr.sy, dr.sz, dr.o[0], dr.o[1], dr.o[2],
+                       dr.e[0], dr.e[1], dr.e[2], axis, n_axis, taps);
+}
+
+// Unfused: x pass over (input z, input y, output x) -> s1; y pass over
+// (input z, output y, output x) -> s2; z pass -> out.
+template <typename Tin, typename Tout>
+void launch_unfused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *scratch)
+{
+    // Input region extent: every reflected index of the output region.
+    // Reflected indices of [o - r, o + e + r) all lie in
+    // [max(o - r, 0), min(o + e + r, n)).
+    int64_t lo[3], hi[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        const int r = taps.r[ax];
+        lo[ax] = a.out_o[ax] - r < 0 ? 0 : a.out_o[ax] - r;
+        hi[ax] = a.out_o[ax] + a.out_e[ax] + r > a.n[ax] ? a.n[ax] : a.out_o[ax] + a.out_e[ax] + r;
+    }
+    Region src{const_cast<void *>(a.in), a.in_sy, a.in_sz, {a.in_o[0], a.in_o[1], a.in_o[2]}, {0, 0, 0}};
+    Region r1{scratch, a.out_e[2], a.out_e[2] * (hi[1] - lo[1]), {lo[0], lo[1], a.out_o[2]},
+              {hi[0] - lo[0], hi[1] - lo[1], a.out_e[2]}};
+    float *s2p = scratch + r1.e[0] * r1.e[1] * r1.e[2];
+    Region r2{s2p, a.out_e[2], a.out_e[2] * a.out_e[1], {lo[0], a.out_o[1], a.out_o[2]},
+              {hi[0] - lo[0], a.out_e[1], a.out_e[2]}};
+    Region dst{a.out, a.out_sy, a.out_sz, {a.out_o[0], a.out_o[1], a.out_o[2]},
+               {a.out_e[0], a.out_e[1], a.out_e[2]}};
+    launch_pass<Tin, float>(static_cast<const Tin *>(a.in), src, scratch, r1, 2, a.n[2], taps, s);
+    launch_pass<float, float>(scratch, r1, s2p, r2, 1, a.n[1], taps, s);
+    launch_pass<float, Tout>(s2p, r2, static_cast<Tout *>(a.out), dst, 0, a.n[0], taps, s);
+}
+
+inline bool fused_ok(const GaussTaps &t, const ChunkArgs &a)
+{
+    if (!(t.r[0] == t.r[1] && t.r[1] == t.r[2])) return false;
+    if (t.r[0] < 1 || t.r[0] > kGaussFusedMaxR) return false;
+    // in-plane offsets are 32-bit
+    return a.in_sy * (a.n[1] + 1) < (int64_t)1 << 31;
+}
+
+template <typename Tin, typename Tout>
+bool run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes)
+{
+    if (fused_ok(taps, a)) return dispatch_fused<Tin, Tout>(taps.r[0], a, taps, s);
+    const int64_t need = (int64_t)gaussian_scratch_bytes(a.out_e, taps.r);
+    if (scratch == nullptr || (int64_t)scratch_bytes < need) return false;
+    launch_unfused<Tin, Tout>(a, taps, s, static_cast<float *>(scratch));
+    return true;
+}
+
+}  // namespace gauss_detail
+
+template <typename Tin, typename Tout>
+bool gauss_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes)
+{
+    return gauss_detail::run<Tin, Tout>(a, taps, s, scratch, scratch_bytes);
+}
+
+}  // namespace harpia

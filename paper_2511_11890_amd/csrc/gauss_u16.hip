@@ -1,0 +1,6 @@
+// Gaussian kernels instantiated for uint16_t -> float.
+#include "gauss_impl.h"
+
+namespace harpia {
+template bool gauss_run<uint16_t, float>(const ChunkArgs &, const GaussTaps &, hipStream_t, void *, size_t);
+}  // namespace harpia

@@ -1,0 +1,661 @@
+// Erosion / dilation kernels for gfx950 (the label-editing module's
+// morphology, Section III-C).  Templates; instantiated per input dtype in
+// morph_<dtype>.hip so the build compiles them in parallel.
+//
+// Definitions: dilation takes the max, erosion the min, of the input over the
+// structuring element B placed at the voxel; B is a box |d_a| <= r or a ball
+// dz^2 + dy^2 + dx^2 <= r^2.  At the faces the input is reflected
+// (half-sample), which for these elements gives the same result as ignoring
+// offsets outside the volume.
+//
+// Single-op kernels compute a dilation; an erosion is the dilation of the
+// negated input, negated back (exact for every dtype: negation is exact in
+// f32 and all u8/u16/f16/bf16 values are f32 values).  Binary erosion is the
+// complement of the dilation of the complement.  "Both" kernels return the
+// erosion and the dilation from one read of the input.
+//
+// Structure (same skeleton as the fused Gaussian): a 256-thread workgroup
+// owns a tile of output columns and streams along z.  Per input slice:
+//   1. the (tile + 2r halo) patch is staged in LDS (reflection on load);
+//   2. stage A: x-run extrema of half-width h for every level h the element
+//      needs (box: h = r only; ball: h = 0..r), from LDS, into LDS planes;
+//   3. stage B: for every z-class c = |dz| the in-plane disc (ball: rows
+//      |dy| <= floor(sqrt(r^2 - c^2)) with x half-width
+//      floor(sqrt(r^2 - c^2 - dy^2)); box: the full square) is the extremum
+//      of the level planes over its rows;
+//   4. z: a register ring of 2r+1 running extrema per column; slice s feeds
+//      class |o - s| into output o, and output s - r is complete.
+// Binary data is packed 4 voxels per 32-bit word (one byte each, 0 or 1):
+// extrema become AND / OR on words and x shifts are byte funnel shifts.
+#pragma once
+
+#include <cstdint>
+#include <utility>
+
+#include "common.h"
+
+namespace harpia {
+
+#ifndef HARPIA_STATIC_FOR_DEFINED
+#define HARPIA_STATIC_FOR_DEFINED
+template <int... I, class F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, F &&f)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(std::make_integer_sequence<int, N>{}, static_cast<F &&>(f));
+}
+#endif
+
+namespace morph_detail {
+
+constexpr int kNT = 256;
+constexpr int kMaxFastR = 4;
+
+constexpr int isqrt_c(int v)
+{
+    int r = 0;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+// Geometry of the element: z-classes, their y half-extent and the x
+// half-width of each of their rows.
+template <int SE, int R>
+struct Shape {
+    static constexpr int NC = (SE == HARPIA_SE_BOX) ? 1 : R + 1;  // z-classes
+    static constexpr int NL = (SE == HARPIA_SE_BOX) ? 1 : R + 1;  // x-run levels
+    static constexpr int cls(int d) { return SE == HARPIA_SE_BOX ? 0 : (d < 0 ? -d : d); }
+    static constexpr int rho(int c) { return SE == HARPIA_SE_BOX ? R : isqrt_c(R * R - c * c); }
+    static constexpr int hw(int c, int dy)
+    {
+        return SE == HARPIA_SE_BOX ? R : isqrt_c(R * R - c * c - dy * dy);
+    }
+    static constexpr int lvl(int h) { return SE == HARPIA_SE_BOX ? 0 : h; }
+};
+
+// Grid shape shared by the launchers: tiles of TX x TY columns, z ranges
+// long enough to amortise the 2r-slice warm-up, enough workgroups to fill
+// the chip.
+struct Grid {
+    int tiles_x, tiles_y;
+    int zlen;
+    int64_t blocks;
+};
+
+inline Grid make_grid(const ChunkArgs &a, int TX, int TY, int R)
+{
+    Grid g;
+    g.tiles_x = (int)((a.out_e[2] + TX - 1) / TX);
+    g.tiles_y = (int)((a.out_e[1] + TY - 1) / TY);
+    const int64_t tiles = (int64_t)g.tiles_x * g.tiles_y;
+    int64_t zlen = a.out_e[0];
+    const int64_t want = 4096;
+    if (tiles < want) {
+        const int64_t nzc = (want + tiles - 1) / tiles;
+        zlen = (a.out_e[0] + nzc - 1) / nzc;
+        const int64_t min_len = 8 * R > 32 ? 8 * R : 32;
+        if (zlen < min_len) zlen = min_len;
+    } else if (zlen > 256) {
+        zlen = 256;
+    }
+    if (zlen > a.out_e[0]) zlen = a.out_e[0];
+    g.zlen = (int)zlen;
+    g.blocks = tiles * ((a.out_e[0] + zlen - 1) / zlen);
+    return g;
+}
+
+// ------------------------------------------------------------- grayscale
+
+constexpr int kGTX = 64, kGTY = 16;
+
+// Second output of the "both" kernels.
+struct Out2 {
+    void *ptr;
+    int64_t sy, sz;
+};
+
+template <typename T, int SE, int R, bool BOTH>
+__global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float sign, int tiles_x, int tiles_y,
+                                                   int zlen)
+{
+    using S = Shape<SE, R>;
+    constexpr int P = 2 * R + 1;
+    constexpr int PW = kGTX + 2 * R;
+    constexpr int PWP = (PW + 3) & ~3;
+    constexpr int PH = kGTY + 2 * R;
+    constexpr int PSZ = PW * PH;
+    constexpr int NLD = (PSZ + kNT - 1) / kNT;
+    constexpr int NA = (kGTX / 4) * PH;  // stage A items (row, quad)
+    constexpr int NV = 4 + 2 * R;
+    constexpr int NV4 = (NV + 3) / 4;
+    constexpr int NM = BOTH ? 2 : 1;      // 0: max (dilation), 1: min
+
+    __shared__ __attribute__((aligned(16))) float sP[PH * PWP + 4 * NV4];
+    __shared__ __attribute__((aligned(16))) float sH[NM][S::NL][PH * kGTX];
+
+    const int tid = threadIdx.x;
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = (int)(b % (uint32_t)tiles_x);
+    const int by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
+    const int bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
+
+    const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
+    const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1];
+    const int64_t x0 = xbeg + (int64_t)bx * kGTX;
+    const int64_t y0 = ybeg + (int64_t)by * kGTY;
+    const int64_t zo0 = a.out_o[0] + (int64_t)bz * zlen;
+    const int64_t zo1 = min(zo0 + (int64_t)zlen, a.out_o[0] + a.out_e[0]);
+    if (zo0 >= zo1) return;
+
+    int32_t off[NLD];
+    int32_t lds[NLD];
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+        const int e = tid + i * kNT;
+        off[i] = 0;
+        lds[i] = 0;
+        if (e < PSZ) {
+            const int row = e / PW, col = e - (e / PW) * PW;
+            int64_t gy = y0 - R + row;
+            gy = gy < ybeg - R ? ybeg - R : (gy > yend - 1 + R ? yend - 1 + R : gy);
+            int64_t gx = x0 - R + col;
+            gx = gx < xbeg - R ? xbeg - R : (gx > xend - 1 + R ? xend - 1 + R : gx);
+            off[i] = (int32_t)((reflect_index(gy, a.n[1]) - a.in_o[1]) * a.in_sy +
+                               (reflect_index(gx, a.n[2]) - a.in_o[2]));
+            lds[i] = row * PWP + col;
+        }
+    }
+
+    const T *in = static_cast<const T *>(a.in);
+    float pf[NLD];
+    auto fetch = [&](int64_t s) __attribute__((always_inline)) {
+        const T *base = in + (reflect_index(s, a.n[0]) - a.in_o[0]) * a.in_sz;
+#pragma unroll
+        for (int i = 0; i < NLD; ++i)
+            if (i < NLD - 1 || tid + i * kNT < PSZ) pf[i] = to_f32(base[off[i]]);
+    };
+
+    const int qrow = tid / (kGTX / 4);
+    const int qcol = (tid % (kGTX / 4)) * 4;
+    const int64_t gy_out = y0 + qrow;
+    const int64_t gx_out = x0 + qcol;
+    const int nvalid = (gy_out < yend) ? (int)min((int64_t)4, xend - gx_out) : 0;
+    T *outp = static_cast<T *>(a.out) + (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
+    T *outp2 = BOTH ? static_cast<T *>(o2.ptr) + (gy_out - ybeg) * o2.sy + (gx_out - xbeg) : nullptr;
+
+    float acc[NM][P][4];
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[m][j][c] = 0.f;
+
+    const int64_t s0 = zo0 - R;
+    const int nsteps = (int)(zo1 - zo0) + 2 * R;
+    fetch(s0);
+
+    for (int base = 0; base < nsteps; base += P) {
+        static_for<P>([&](auto U) {
+            constexpr int u = decltype(U)::value;
+            const int i = base + u;
+            if (i >= nsteps) return;
+
+            // 1. stage (with the sign flip of a single erosion)
+#pragma unroll
+            for (int k = 0; k < NLD; ++k)
+                if (k < NLD - 1 || tid + k * kNT < PSZ) sP[lds[k]] = BOTH ? pf[k] : sign * pf[k];
+            if (i + 1 < nsteps) fetch(s0 + i + 1);
+            __syncthreads();
+
+            // 2. stage A: x-run extrema of every level on all patch rows
+            for (int it = tid; it < NA; it += kNT) {
+                const int row = it / (kGTX / 4);
+                const int c0 = (it % (kGTX / 4)) * 4;
+                float v[NV4 * 4];
+                const float4 *p4 = reinterpret_cast<const float4 *>(&sP[row * PWP + c0]);
+#pragma unroll
+                for (int j = 0; j < NV4; ++j) {
+                    const float4 t4 = p4[j];
+                    v[4 * j] = t4.x;
+                    v[4 * j + 1] = t4.y;
+                    v[4 * j + 2] = t4.z;
+                    v[4 * j + 3] = t4.w;
+                }
+#pragma unroll
+                for (int m = 0; m < NM; ++m) {
+                    float run[4], res[S::NL][4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) run[c] = v[c + R];
+                    static_for<R + 1>([&](auto H) {
+                        constexpr int h = decltype(H)::value;
+                        if constexpr (h > 0) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                run[c] = (m == 0) ? fmaxf(run[c], fmaxf(v[c + R - h], v[c + R + h]))
+                                                  : fminf(run[c], fminf(v[c + R - h], v[c + R + h]));
+                        }
+                        if constexpr (SE != HARPIA_SE_BOX || h == R) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) res[S::lvl(h)][c] = run[c];
+                        }
+                    });
+#pragma unroll
+                    for (int l = 0; l < S::NL; ++l)
+                        *reinterpret_cast<float4 *>(&sH[m][l][row * kGTX + c0]) =
+                            make_float4(res[l][0], res[l][1], res[l][2], res[l][3]);
+                }
+            }
+            __syncthreads();
+
+            // 3. stage B: in-plane disc of every z-class, 4 columns
+            float D[NM][S::NC][4];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                static_for<S::NC>([&](auto C) {
+                    constexpr int c = decltype(C)::value;
+                    constexpr int rh = S::rho(c);
+                    float dv[4];
+                    static_for<2 * rh + 1>([&](auto DY) {
+                        constexpr int dy = decltype(DY)::value - rh;
+                        constexpr int l = S::lvl(S::hw(c, dy));
+                        const float4 t4 =
+                            *reinterpret_cast<const float4 *>(&sH[m][l][(qrow + R + dy) * kGTX + qcol]);
+                        const float tv[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            if constexpr (dy == -rh) dv[q] = tv[q];
+                            else dv[q] = (m == 0) ? fmaxf(dv[q], tv[q]) : fminf(dv[q], tv[q]);
+                        }
+                    });
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) D[m][c][q] = dv[q];
+                });
+            }
+
+            // 4. z ring
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                static_for<P>([&](auto DD) {
+                    constexpr int d = decltype(DD)::value - R;
+                    constexpr int sl = (u + d + 2 * P) % P;
+                    constexpr int c = S::cls(d);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[m][sl][q] = (d == R) ? D[m][c][q]
+                                                 : ((m == 0) ? fmaxf(acc[m][sl][q], D[m][c][q])
+                                                             : fminf(acc[m][sl][q], D[m][c][q]));
+                });
+            }
+            if (i >= 2 * R && nvalid > 0) {
+                constexpr int sl = (u - R + 2 * P) % P;
+                const int64_t zl = s0 + i - R - a.out_o[0];
+                if constexpr (BOTH) {
+                    // out = erosion (min), out2 = dilation (max)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (q < nvalid) {
+                            outp[zl * a.out_sz + q] = from_f32<T>(acc[1][sl][q]);
+                            outp2[zl * o2.sz + q] = from_f32<T>(acc[0][sl][q]);
+                        }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (q < nvalid) outp[zl * a.out_sz + q] = from_f32<T>(sign * acc[0][sl][q]);
+                }
+            }
+        });
+    }
+}
+
+// ---------------------------------------------------------------- binary
+
+constexpr int kBTX = 256;             // voxels per tile row (64 words)
+constexpr int kBTY = 16;
+constexpr int kBW = kBTX / 4;         // words per tile row
+constexpr int kBPW = kBW + 2;         // patch words per row (1 halo word a side)
+
+__device__ __forceinline__ uint32_t funnel_bytes(uint32_t hi, uint32_t lo, int k)
+{
+    // bytes k..k+3 of the 8-byte little-endian value hi:lo (0 <= k <= 4)
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> (8 * k));
+}
+
+// Store 16 output bytes (4 packed words), or the first `nvalid` of them.
+__device__ __forceinline__ void emit16(uint8_t *p, uint4 w, int nvalid)
+{
+    if (nvalid == 16 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+        *reinterpret_cast<uint4 *>(p) = w;
+        return;
+    }
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        if (q < nvalid) p[q] = (uint8_t)((ws[q >> 2] >> (8 * (q & 3))) & 0xffu);
+}
+
+template <typename Tin>
+__device__ __forceinline__ uint32_t binarise(Tin v, float thr, bool use_thr)
+{
+    const float f = to_f32(v);
+    return use_thr ? (f > thr ? 1u : 0u) : (f != 0.f ? 1u : 0u);
+}
+
+// Binary erosion / dilation: u8 {0, 1} output.  `flip` = 1 computes an
+// erosion (complement in and out), 0 a dilation; BOTH writes the erosion to
+// out and the dilation to out2.
+template <typename Tin, int SE, int R, bool BOTH>
+__global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint32_t flip, float thr, int use_thr,
+                                                     int tiles_x, int tiles_y, int zlen)
+{
+    static_assert(R >= 1 && R <= 4, "one halo word per side");
+    using S = Shape<SE, R>;
+    constexpr int P = 2 * R + 1;
+    constexpr int PH = kBTY + 2 * R;
+    constexpr int NWI = kBPW * PH;                 // patch words
+    constexpr int NLW = (NWI + kNT - 1) / kNT;     // words loaded per thread
+    constexpr int NA = kBW * PH;                   // stage A items
+    constexpr int NM = BOTH ? 2 : 1;               // 0: OR (dilation), 1: AND
+    const uint32_t fmask = flip ? 0x01010101u : 0u;
+
+    __shared__ uint32_t sP[PH * kBPW];
+    __shared__ __attribute__((aligned(16))) uint32_t sH[NM][S::NL][PH * kBW];
+
+    const int tid = threadIdx.x;
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = (int)(b % (uint32_t)tiles_x);
+    const int by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
+    const int bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
+
+    const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
+    const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1];
+    const int64_t x0 = xbeg + (int64_t)bx * kBTX;
+    const int64_t y0 = ybeg + (int64_t)by * kBTY;
+    const int64_t zo0 = a.out_o[0] + (int64_t)bz * zlen;
+    const int64_t zo1 = min(zo0 + (int64_t)zlen, a.out_o[0] + a.out_e[0]);
+    if (zo0 >= zo1) return;
+
+    // Each loaded word holds patch columns 4w-4 .. 4w-1 relative to x0.  Its
+    // source offset is kept when the 4 voxels are consecutive in memory;
+    // words that cross a face or the clamp (-1) are resolved per voxel.
+    int32_t off[NLW];
+#pragma unroll
+    for (int i = 0; i < NLW; ++i) {
+        const int e = tid + i * kNT;
+        off[i] = 0;
+        if (e < NWI) {
+            const int row = e / kBPW, w = e - (e / kBPW) * kBPW;
+            int64_t gy = y0 - R + row;
+            gy = gy < ybeg - R ? ybeg - R : (gy > yend - 1 + R ? yend - 1 + R : gy);
+            const int64_t ly = reflect_index(gy, a.n[1]) - a.in_o[1];
+            const int64_t gx = x0 - 4 + 4 * w;
+            if (gx >= 0 && gx + 3 < a.n[2] && gx >= xbeg - R && gx + 3 <= xend - 1 + R)
+                off[i] = (int32_t)(ly * a.in_sy + (gx - a.in_o[2]));
+            else
+                off[i] = -1 - (int32_t)ly;  // slow path marker, keeps the row
+        }
+    }
+
+    const Tin *in = static_cast<const Tin *>(a.in);
+    uint32_t pf[NLW];
+    auto fetch = [&](int64_t s) __attribute__((always_inline)) {
+        const Tin *base = in + (reflect_index(s, a.n[0]) - a.in_o[0]) * a.in_sz;
+#pragma unroll
+        for (int i = 0; i < NLW; ++i) {
+            if (i < NLW - 1 || tid + i * kNT < NWI) {
+                uint32_t wv = 0;
+                if (off[i] >= 0) {
+                    const Tin *p = base + off[i];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) wv |= binarise(p[j], thr, use_thr) << (8 * j);
+                } else {
+                    const int e = tid + i * kNT;
+                    const int w = e % kBPW;
+                    const int64_t ly = -1 - (int64_t)off[i];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        int64_t gx = x0 - 4 + 4 * w + j;
+                        gx = gx < xbeg - R ? xbeg - R : (gx > xend - 1 + R ? xend - 1 + R : gx);
+                        const int64_t lx = reflect_index(gx, a.n[2]) - a.in_o[2];
+                        wv |= binarise(base[ly * a.in_sy + lx], thr, use_thr) << (8 * j);
+                    }
+                }
+                pf[i] = wv;
+            }
+        }
+    };
+
+    const int qrow = tid / (kBW / 4);
+    const int qw = (tid % (kBW / 4)) * 4;  // first word of this thread's quad
+    const int64_t gy_out = y0 + qrow;
+    const int64_t gx_out = x0 + 4 * qw;
+    const int nvalid = (gy_out < yend) ? (int)min((int64_t)16, xend - gx_out) : 0;
+    uint8_t *outp = static_cast<uint8_t *>(a.out) + (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
+    uint8_t *outp2 = BOTH ? static_cast<uint8_t *>(o2.ptr) + (gy_out - ybeg) * o2.sy + (gx_out - xbeg) : nullptr;
+
+    uint32_t acc[NM][P][4];
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[m][j][c] = 0u;
+
+    const int64_t s0 = zo0 - R;
+    const int nsteps = (int)(zo1 - zo0) + 2 * R;
+    fetch(s0);
+
+    for (int base = 0; base < nsteps; base += P) {
+        static_for<P>([&](auto U) {
+            constexpr int u = decltype(U)::value;
+            const int i = base + u;
+            if (i >= nsteps) return;
+
+#pragma unroll
+            for (int k = 0; k < NLW; ++k)
+                if (k < NLW - 1 || tid + k * kNT < NWI) sP[tid + k * kNT] = BOTH ? pf[k] : (pf[k] ^ fmask);
+            if (i + 1 < nsteps) fetch(s0 + i + 1);
+            __syncthreads();
+
+            // stage A: word-level x runs (OR for m = 0, AND for m = 1)
+            for (int it = tid; it < NA; it += kNT) {
+                const int row = it / kBW, w = it - (it / kBW) * kBW;
+                const uint32_t wl = sP[row * kBPW + w];
+                const uint32_t wc = sP[row * kBPW + w + 1];
+                const uint32_t wr = sP[row * kBPW + w + 2];
+#pragma unroll
+                for (int m = 0; m < NM; ++m) {
+                    uint32_t run = wc;
+                    static_for<R + 1>([&](auto H) {
+                        constexpr int h = decltype(H)::value;
+                        if constexpr (h > 0) {
+                            const uint32_t sr = funnel_bytes(wr, wc, h);      // voxel x + h
+                            const uint32_t sl2 = funnel_bytes(wc, wl, 4 - h); // voxel x - h
+                            run = (m == 0) ? (run | sr | sl2) : (run & sr & sl2);
+                        }
+                        if constexpr (SE != HARPIA_SE_BOX || h == R) sH[m][S::lvl(h)][row * kBW + w] = run;
+                    });
+                }
+            }
+            __syncthreads();
+
+            uint32_t D[NM][S::NC][4];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                static_for<S::NC>([&](auto C) {
+                    constexpr int c = decltype(C)::value;
+                    constexpr int rh = S::rho(c);
+                    uint32_t dv[4];
+                    static_for<2 * rh + 1>([&](auto DY) {
+                        constexpr int dy = decltype(DY)::value - rh;
+                        constexpr int l = S::lvl(S::hw(c, dy));
+                        const uint4 t4 = *reinterpret_cast<const uint4 *>(&sH[m][l][(qrow + R + dy) * kBW + qw]);
+                        const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            if constexpr (dy == -rh) dv[q] = tv[q];
+                            else dv[q] = (m == 0) ? (dv[q] | tv[q]) : (dv[q] & tv[q]);
+                        }
+                    });
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) D[m][c][q] = dv[q];
+                });
+            }
+
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                static_for<P>([&](auto DD) {
+                    constexpr int d = decltype(DD)::value - R;
+                    constexpr int sl = (u + d + 2 * P) % P;
+                    constexpr int c = S::cls(d);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[m][sl][q] = (d == R) ? D[m][c][q]
+                                                 : ((m == 0) ? (acc[m][sl][q] | D[m][c][q])
+                                                             : (acc[m][sl][q] & D[m][c][q]));
+                });
+            }
+            if (i >= 2 * R && nvalid > 0) {
+                constexpr int sl = (u - R + 2 * P) % P;
+                const int64_t zl = s0 + i - R - a.out_o[0];
+                if constexpr (BOTH) {
+                    emit16(outp + zl * a.out_sz, make_uint4(acc[1][sl][0], acc[1][sl][1], acc[1][sl][2], acc[1][sl][3]),
+                           nvalid);
+                    emit16(outp2 + zl * o2.sz, make_uint4(acc[0][sl][0], acc[0][sl][1], acc[0][sl][2], acc[0][sl][3]),
+                           nvalid);
+                } else {
+                    emit16(outp + zl * a.out_sz,
+                           make_uint4(acc[0][sl][0] ^ fmask, acc[0][sl][1] ^ fmask, acc[0][sl][2] ^ fmask,
+                                      acc[0][sl][3] ^ fmask),
+                           nvalid);
+                }
+            }
+        });
+    }
+}
+
+// --------------------------------------------------------------- generic
+
+// Any radii (anisotropic boxes, radii beyond the fast kernels): direct
+// extremum over the element, skipping offsets outside the volume (equal to
+// the reflect boundary for these elements).  mode 0: dilation (or erosion of
+// sign-flipped data), 2: both.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void morph_generic_kernel(ChunkArgs a, Out2 o2, int se, int rz, int ry, int rx,
+                                                            int both, float sign, int binary, float thr,
+                                                            int use_thr, uint32_t flip)
+{
+    const int64_t ez = a.out_e[0], ey = a.out_e[1], ex = a.out_e[2];
+    const int64_t total = ez * ey * ex;
+    const Tin *in = static_cast<const Tin *>(a.in);
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = id % ex, y = (id / ex) % ey, z = id / (ex * ey);
+        const int64_t gz = a.out_o[0] + z, gy = a.out_o[1] + y, gx = a.out_o[2] + x;
+        float mx = -INFINITY, mn = INFINITY;
+        for (int dz = -rz; dz <= rz; ++dz) {
+            const int64_t zz = gz + dz;
+            if (zz < 0 || zz >= a.n[0]) continue;
+            for (int dy = -ry; dy <= ry; ++dy) {
+                const int64_t yy = gy + dy;
+                if (yy < 0 || yy >= a.n[1]) continue;
+                for (int dx = -rx; dx <= rx; ++dx) {
+                    const int64_t xx = gx + dx;
+                    if (xx < 0 || xx >= a.n[2]) continue;
+                    if (se == HARPIA_SE_BALL && dz * dz + dy * dy + dx * dx > rz * rz) continue;
+                    const Tin raw = in[(zz - a.in_o[0]) * a.in_sz + (yy - a.in_o[1]) * a.in_sy + (xx - a.in_o[2])];
+                    float v = binary ? (float)(binarise(raw, thr, use_thr) ^ flip) : sign * to_f32(raw);
+                    mx = fmaxf(mx, v);
+                    mn = fminf(mn, v);
+                }
+            }
+        }
+        Tout *op = static_cast<Tout *>(a.out) + z * a.out_sz + y * a.out_sy + x;
+        if (both) {
+            *op = from_f32<Tout>(mn);
+            static_cast<Tout *>(o2.ptr)[z * o2.sz + y * o2.sy + x] = from_f32<Tout>(mx);
+        } else if (binary) {
+            *op = from_f32<Tout>((float)((uint32_t)mx ^ flip));
+        } else {
+            *op = from_f32<Tout>(sign * mx);
+        }
+    }
+}
+
+}  // namespace morph_detail
+
+namespace morph_detail {
+
+template <typename T, int SE, int R, bool BOTH>
+void launch_fast(const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float thr_f, hipStream_t s)
+{
+    if (m.binary) {
+        const Grid g = make_grid(a, kBTX, kBTY, R);
+        hipLaunchKernelGGL((binary_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, o2,
+                           (uint32_t)(m.op == 0 ? 1u : 0u), thr_f, (int)m.has_threshold, g.tiles_x, g.tiles_y,
+                           g.zlen);
+    } else {
+        const Grid g = make_grid(a, kGTX, kGTY, R);
+        hipLaunchKernelGGL((gray_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, o2,
+                           m.op == 0 ? -1.f : 1.f, g.tiles_x, g.tiles_y, g.zlen);
+    }
+}
+
+template <typename T, int SE, bool BOTH>
+bool dispatch_r(int r, const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float thr_f, hipStream_t s)
+{
+    switch (r) {
+    case 1: launch_fast<T, SE, 1, BOTH>(a, m, o2, thr_f, s); return true;
+    case 2: launch_fast<T, SE, 2, BOTH>(a, m, o2, thr_f, s); return true;
+    case 3: launch_fast<T, SE, 3, BOTH>(a, m, o2, thr_f, s); return true;
+    case 4: launch_fast<T, SE, 4, BOTH>(a, m, o2, thr_f, s); return true;
+    default: return false;
+    }
+}
+
+template <typename T>
+bool run(const ChunkArgs &a, const MorphSpec &m, bool both, const Region *out2, float thr_f, hipStream_t s)
+{
+    if (a.out_e[0] <= 0 || a.out_e[1] <= 0 || a.out_e[2] <= 0) return true;
+    Out2 o2{nullptr, 0, 0};
+    if (out2) {
+        o2.ptr = out2->ptr;
+        o2.sy = out2->sy;
+        o2.sz = out2->sz;
+    }
+    const bool iso = m.r[0] == m.r[1] && m.r[1] == m.r[2];
+    const bool small_slice = a.in_sy * (a.n[1] + 1) < ((int64_t)1 << 31);
+    if (iso && m.r[0] >= 1 && m.r[0] <= kMaxFastR && small_slice) {
+        if (m.se == HARPIA_SE_BOX)
+            return both ? dispatch_r<T, HARPIA_SE_BOX, true>(m.r[0], a, m, o2, thr_f, s)
+                        : dispatch_r<T, HARPIA_SE_BOX, false>(m.r[0], a, m, o2, thr_f, s);
+        return both ? dispatch_r<T, HARPIA_SE_BALL, true>(m.r[0], a, m, o2, thr_f, s)
+                    : dispatch_r<T, HARPIA_SE_BALL, false>(m.r[0], a, m, o2, thr_f, s);
+    }
+    const int64_t total = a.out_e[0] * a.out_e[1] * a.out_e[2];
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    const float sign = (!both && m.op == 0) ? -1.f : 1.f;
+    const uint32_t flip = (m.binary && !both && m.op == 0) ? 1u : 0u;
+    if (m.binary)
+        hipLaunchKernelGGL((morph_generic_kernel<T, uint8_t>), dim3((uint32_t)blocks), dim3(256), 0, s, a, o2, m.se,
+                           m.r[0], m.r[1], m.r[2], (int)both, 1.f, 1, thr_f, (int)m.has_threshold, flip);
+    else
+        hipLaunchKernelGGL((morph_generic_kernel<T, T>), dim3((uint32_t)blocks), dim3(256), 0, s, a, o2, m.se,
+                           m.r[0], m.r[1], m.r[2], (int)both, sign, 0, thr_f, 0, 0u);
+    return true;
+}
+
+}  // namespace morph_detail
+
+template <typename T>
+bool morph_run(const ChunkArgs &a, const MorphSpec &m, bool both, const Region *out2, float thr_f, hipStream_t s)
+{
+    return morph_detail::run<T>(a, m, both, out2, thr_f, s);
+}
+
+}  // namespace harpia

@@ -43,18 +43,20 @@ def _torch_gen(seed: int, stream: int, device) -> torch.Generator:
 
 
 def blobs(n: int = 128, n_blobs: int = 40, noise: float = 0.05,
-          seed: int = 0) -> np.ndarray:
-    """Sum of isotropic Gaussian blobs plus white noise (float32, [n, n, n])."""
+          seed: int = 0, shape=None) -> np.ndarray:
+    """Sum of isotropic Gaussian blobs plus white noise (float32, [n, n, n],
+    or `shape` with centres uniform over each extent)."""
+    shape = (n, n, n) if shape is None else tuple(int(s) for s in shape)
     rng = _rng(seed, 1)
-    centres = rng.uniform(0.0, n, size=(n_blobs, 3))
+    centres = rng.uniform(0.0, 1.0, size=(n_blobs, 3)) * np.array(shape, dtype=np.float64)
     widths = rng.uniform(4.0, 12.0, size=n_blobs)
     amps = rng.uniform(0.2, 1.0, size=n_blobs)
-    ax = np.arange(n, dtype=np.float64)
-    v = np.zeros((n, n, n), dtype=np.float64)
+    axes = [np.arange(s, dtype=np.float64) for s in shape]
+    v = np.zeros(shape, dtype=np.float64)
     for (cz, cy, cx), s, a in zip(centres, widths, amps):
-        ez = np.exp(-((ax - cz) ** 2) / (2 * s * s))
-        ey = np.exp(-((ax - cy) ** 2) / (2 * s * s))
-        ex = np.exp(-((ax - cx) ** 2) / (2 * s * s))
+        ez = np.exp(-((axes[0] - cz) ** 2) / (2 * s * s))
+        ey = np.exp(-((axes[1] - cy) ** 2) / (2 * s * s))
+        ex = np.exp(-((axes[2] - cx) ** 2) / (2 * s * s))
         v += a * ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
     v += rng.normal(0.0, noise, size=v.shape)
     return v.astype(np.float32)
