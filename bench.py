@@ -1,0 +1,280 @@
+"""Throughput of the volumetric filtering hot path on one MI355X.
+
+Default workload (resident, one GPU): a 1024^3 float32 two-phase porous
+phantom in HBM; one step = Gaussian smoothing with sigma 1, 2 and 4 (truncate
+3, reflect) plus grayscale erosion and dilation with the ball of radius 3
+(one fused launch, two outputs).  value = output voxels of the step (5 x
+1024^3) per second, in GVox/s.
+
+Per-op times are measured with HIP events on the stream the library launches
+on (torch's current stream).  The roofline block reports the op with the
+largest share of the step: algorithmic bytes (or multiply-adds) per launch
+over its average event-timed duration, against the MI355X peak.  The CPU
+baseline is the FP64 oracle on a bounded slab of the same phantom, timed on
+this host's cores.
+
+Other workloads (--workload): "precision" (2048^3 bf16 / f16 / f32 Gaussian
+sigma 1 and 4), "chunked" (2048^3 uint16 in pinned host memory, 8 GiB device
+budget, 512^3 bricks: Gaussian sigma 2 to float32 and binary opening with the
+radius-2 ball on threshold 32768).
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GVox/s plain FP32 vs BF16+fused fwd/bwd filter at stated err; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+# fp32 vector peak of the chip: 256 CU x 4 SIMD x 16 lanes x 2 (packed dual
+# FP32) x 2 flop per FMA x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+KERNEL_SOURCES = {
+    "gauss": ["paper_2511_11890_amd/csrc/gauss_impl.h", "paper_2511_11890_amd/csrc/gauss_f32.hip"],
+    "morph": ["paper_2511_11890_amd/csrc/morph_impl.h", "paper_2511_11890_amd/csrc/morph_f32.hip"],
+}
+
+
+def sources_sha(kind: str) -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(op_name: str, kind: str, launches_voxels: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.json")):
+        try:
+            d = json.load(open(path))
+        except Exception:
+            continue
+        if d.get("op") == op_name and d.get("source_sha") == sources_sha(kind):
+            return d.get("hbm_bytes_per_launch")
+    return None
+
+
+def cpu_baseline(v_dev, sample_slices: int = 24):
+    """FP64 oracle on a z-slab of the phantom: Gaussian sigma 1, 2, 4
+    (separable, pinned equal to the direct form) and ball-3 erosion and
+    dilation (brute force).  The slab is reflected at its own faces, which
+    does not change the work per voxel."""
+    import numpy as np
+
+    import oracle
+
+    v = v_dev[:sample_slices].double().cpu().numpy()
+    t0 = time.perf_counter()
+    for s in (1.0, 2.0, 4.0):
+        oracle.gaussian3d(v, s, method="separable")
+    oracle.erode3d(v, "ball", 3)
+    oracle.dilate3d(v, "ball", 3)
+    dt = time.perf_counter() - t0
+    vox = int(np.prod(v.shape))
+    return {"value": round(5 * vox / dt / 1e9, 6), "unit": "GVox/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%dx%dx%d slab of the 1024^3 phantom: separable FP64 Gaussian sigma 1,2,4 + "
+                      "brute-force ball-3 erosion and dilation, %.1f s" % (v.shape + (dt,))}
+
+
+def run_resident(args):
+    import torch
+
+    import paper_2511_11890_amd as h
+    from paper_2511_11890_amd import phantoms
+
+    dev = torch.device("cuda:0")
+    n = args.size
+    shape = (n, n, n)
+    v = phantoms.porous(shape, seed=0, device=dev)
+    vox = v.numel()
+    outs = {s: torch.empty_like(v) for s in (1.0, 2.0, 4.0)}
+    ero, dil = torch.empty_like(v), torch.empty_like(v)
+
+    def op_gauss(s):
+        h.gaussian(v, s, out=outs[s])
+
+    def op_morph():
+        h._lib.check(h._lib.load().harpia_erode_dilate3d(
+            v.data_ptr(), ero.data_ptr(), dil.data_ptr(), h._lib.HARPIA_F32, h._lib.i64_3(shape),
+            h._lib.HARPIA_SE_BALL, h._lib.i32_3((3, 3, 3)), float("nan"), 0,
+            h._lib.make_exec(stream=torch.cuda.current_stream().cuda_stream)))
+
+    ops = [("gauss_s1", lambda: op_gauss(1.0), 3), ("gauss_s2", lambda: op_gauss(2.0), 6),
+           ("gauss_s4", lambda: op_gauss(4.0), 12), ("erode_dilate_ball3", op_morph, 3)]
+    outputs_per_step = 5
+
+    for _ in range(args.warmup):
+        for _, fn, _ in ops:
+            fn()
+    torch.cuda.synchronize()
+
+    events = {name: [] for name, _, _ in ops}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for name, fn, _ in ops:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            events[name].append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1000.0 / args.steps
+
+    per_op = {}
+    for name, _, r in ops:
+        ms = sum(a.elapsed_time(b) for a, b in events[name]) / len(events[name])
+        nout = 2 if name.startswith("erode_dilate") else 1
+        alg_bytes = vox * (4 + 4 * nout)
+        d = {"ms": round(ms, 4), "gvox_s": round(nout * vox / ms / 1e6, 2),
+             "hbm_gbs": round(alg_bytes / ms / 1e6, 1),
+             "hbm_frac": round(alg_bytes / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        if name.startswith("gauss"):
+            macs = 3 * (2 * r + 1) * vox  # multiply-adds of the separable form
+            d["tflops"] = round(2 * macs / ms / 1e9, 2)
+            d["valu_frac"] = round(2 * macs / ms / 1e9 / FP32_VECTOR_PEAK_TFLOPS, 4)
+        per_op[name] = d
+
+    dom = max(per_op, key=lambda k: per_op[k]["ms"])
+    dd = per_op[dom]
+    kind = "gauss" if dom.startswith("gauss") else "morph"
+    nout = 2 if kind == "morph" else 1
+    alg_bytes = vox * (4 + 4 * nout)
+    if kind == "gauss" and dd["hbm_frac"] < dd["valu_frac"] * 2:
+        r = dict((nm, rr) for nm, _, rr in ops)[dom]
+        macs = 3 * (2 * r + 1) * vox
+        roof = {"bound": "alu", "kernel": dom, "achieved": dd["tflops"], "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(dd["tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "per_launch": {"macs": macs, "bytes": alg_bytes, "ms": dd["ms"]}}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": dd["hbm_gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(dd["hbm_gbs"] / HBM_PEAK_GBS, 4),
+                "per_launch": {"bytes": alg_bytes, "ms": dd["ms"]}}
+    tb = traffic_for(dom, kind, vox)
+    roof["traffic"] = tb
+
+    value = outputs_per_step * vox / (ms_step / 1000.0) / 1e9
+    line = {"metric": METRIC, "value": round(value, 2), "unit": "GVox/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "resident %d^3 float32 porous phantom: Gaussian sigma 1,2,4 + "
+                                   "grayscale erode+dilate ball r=3" % n, "voxels": vox,
+                       "outputs_per_step": outputs_per_step},
+            "roofline": roof, "ops": per_op}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(v)
+    return line
+
+
+def run_precision(args):
+    import torch
+
+    import paper_2511_11890_amd as h
+    from paper_2511_11890_amd import phantoms
+
+    dev = torch.device("cuda:0")
+    n = args.size
+    v = torch.clamp(phantoms.porous((n, n, n), seed=0, device=dev), 0, 1)
+    res = {}
+    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16), ("f16", torch.float16)):
+        x = v.to(dt)
+        for s in (1.0, 4.0):
+            out = torch.empty_like(x)
+            for _ in range(args.warmup):
+                h.gaussian(x, s, out=out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                h.gaussian(x, s, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            es = x.element_size()
+            res["%s_sigma%g" % (name, s)] = {"ms": round(ms, 3), "gvox_s": round(x.numel() / ms / 1e6, 1),
+                                             "hbm_frac": round(2 * es * x.numel() / ms / 1e6 / HBM_PEAK_GBS, 4)}
+            del out
+        del x
+    step_ms = sum(d["ms"] for k, d in res.items() if k.startswith("bf16"))
+    return {"metric": METRIC, "value": round(2 * v.numel() / step_ms / 1e6, 2), "unit": "GVox/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_ms, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+            "data": "synthetic",
+            "config": {"workload": "precision: %d^3 bf16 Gaussian sigma 1 and 4 (f32, f16 for comparison)" % n},
+            "ops": res}
+
+
+def run_chunked(args):
+    import torch
+
+    import paper_2511_11890_amd as h
+    from paper_2511_11890_amd import phantoms
+
+    n = args.size
+    dev = torch.device("cuda:0")
+    v = phantoms.porous_u16((n, n, n), seed=0, device=dev)
+    host = torch.empty((n, n, n), dtype=torch.uint16, pin_memory=True)
+    host.copy_(v)
+    del v
+    torch.cuda.empty_cache()
+    out_g = torch.empty((n, n, n), dtype=torch.float32, pin_memory=True)
+    out_o = torch.empty((n, n, n), dtype=torch.uint8, pin_memory=True)
+    budget = 8 << 30
+    res = {}
+    for name, fn in (("gauss_s2", lambda ex: h.gaussian(host, 2.0, out=out_g, ex=ex)),
+                     ("open_ball2", lambda ex: h.opening(host, "ball", 2, threshold=32768.0, out=out_o, ex=ex))):
+        for label, chunk, bud in (("chunked_512", (512, 512, 512), budget), ("chunked_zslab", (0, 0, 0), budget),
+                                  ("resident", (n, n, n), 200 << 30)):
+            st = h.harpia_stats()
+            fn(h.Exec(budget=bud, chunk=chunk, stats=st))
+            t0 = time.perf_counter()
+            st = h.harpia_stats()
+            fn(h.Exec(budget=bud, chunk=chunk, stats=st))
+            dt = time.perf_counter() - t0
+            res["%s_%s" % (name, label)] = {"s": round(dt, 3), "gvox_s": round(n ** 3 / dt / 1e9, 2),
+                                            "chunks": st.n_chunks, "peak_gib": round(st.peak_device_bytes / 2 ** 30, 2),
+                                            "h2d_gb": round(st.bytes_h2d / 1e9, 2),
+                                            "d2h_gb": round(st.bytes_d2h / 1e9, 2)}
+    tot = res["gauss_s2_chunked_512"]["s"] + res["open_ball2_chunked_512"]["s"]
+    return {"metric": METRIC, "value": round(2 * n ** 3 / tot / 1e9, 2), "unit": "GVox/s", "n_gpus": 1,
+            "steps": 1, "warmup": 1, "ms_per_step": round(tot * 1000, 1), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
+            "config": {"workload": "chunked %d^3 uint16 pinned host, 8 GiB budget, 512^3 bricks: Gaussian "
+                                   "sigma 2 -> f32 + binary opening ball r=2 at 32768" % n},
+            "ops": res}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="resident", choices=["resident", "precision", "chunked"])
+    ap.add_argument("--size", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build runs no multi-GPU path (one process, one device). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.size == 0:
+        args.size = 1024 if args.workload == "resident" else 2048
+    fn = {"resident": run_resident, "precision": run_precision, "chunked": run_chunked}[args.workload]
+    print(json.dumps(fn(args)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -205,6 +205,50 @@ harpia_status harpia_morph3d(const void *in, void *out, harpia_dtype t,
                              double threshold, harpia_border border,
                              const harpia_exec *ex);
 
+/* ------------------------------------------------------------------
+ * Gradients (an extension beyond the paper: differentiable filters).
+ * Both run on device-resident volumes (device pointers; otherwise
+ * HARPIA_ERR_UNSUPPORTED), on ex->stream.  When they allocate scratch they
+ * synchronise ex->stream before freeing it, so they return with the results
+ * complete.
+ * ------------------------------------------------------------------ */
+
+/* Gradient of y = G_sigma x (harpia_gaussian3d) for an upstream gradient
+ * grad_out = dL/dy (float32):
+ *   grad_in = G^T grad_out.  Under the half-sample reflect boundary every 1D
+ *     factor of G is a symmetric matrix, so this is the same Gaussian applied
+ *     to grad_out.  May be NULL.  float32.
+ *   grad_sigma[a] = sum_p grad_out[p] * (d/d sigma_a (G x))[p] with the
+ *     radii held fixed (d w_k / d sigma = w_k (k^2 - sum_j w_j j^2) / sigma^3),
+ *     a = z, y, x; an isotropic sigma's gradient is the sum of the three.
+ *     FP32 products summed per workgroup, workgroup partials summed in FP64
+ *     in a fixed order (deterministic).  May be NULL, a host pointer (filled
+ *     before return) or a device pointer (written on ex->stream).
+ * x (dtype x_t, as for harpia_gaussian3d) is needed only for grad_sigma.
+ * radius[3]: the radii the forward used (resolve them once with
+ * harpia_gauss_radius and keep them; they are not recomputed from sigma). */
+harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t,
+                                         const void *grad_out, void *grad_in,
+                                         const int64_t shape[3],
+                                         const double sigma[3],
+                                         const int32_t radius[3],
+                                         double *grad_sigma,
+                                         const harpia_exec *ex);
+
+/* Subgradient of erosion (op = HARPIA_ERODE) or dilation of `in` (dtype t,
+ * grayscale): every output voxel p sends grad_out[p] to the input voxel that
+ * supplied its extremum, the first in lexicographic (dz, dy, dx) order over
+ * the element's offsets inside the volume (ties go to the earliest offset):
+ *   grad_in[j] = sum of grad_out[p] over the outputs p that chose j,
+ * summed in a fixed order (no atomics; deterministic).  grad_out and grad_in
+ * are float32.  Radii up to 8 per axis. */
+harpia_status harpia_morph3d_backward(const void *in, harpia_dtype t,
+                                      const void *grad_out, void *grad_in,
+                                      const int64_t shape[3],
+                                      harpia_morph_op op, harpia_se se,
+                                      const int32_t radius[3],
+                                      const harpia_exec *ex);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,15 +9,14 @@ and allocates outputs.
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 
 from . import _lib
 from ._lib import HarpiaError, harpia_plan, harpia_stats
 
 __all__ = ["gaussian", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
-           "plan", "gauss_radius", "version", "HarpiaError", "harpia_stats", "Exec"]
+           "plan", "gauss_radius", "version", "HarpiaError", "harpia_stats", "Exec",
+           "gaussian_backward", "morph_backward", "GaussianFn", "MorphFn", "GaussDilateFn"]
 
 
 def _torch():
@@ -253,6 +252,175 @@ def plan(shape, in_dtype="f32", out_dtype="f32", halo=(0, 0, 0), budget: int = 0
     _lib.check(_lib.load().harpia_chunk_plan(_lib.i64_3(shape), _code(in_dtype), _code(out_dtype),
                                             _lib.i32_3(_triple(halo, int)), e, p))
     return p
+
+
+def gaussian_backward(x, grad_out, sigma, radius, grad_in=True, grad_sigma=True, ex: Exec | None = None):
+    """Gradients of y = gaussian(x, sigma) with the radii held fixed:
+    (G^T grad_out or None, float64 tensor [3] of dL/d sigma_{z,y,x} or None).
+    Device tensors only; grad_out float32."""
+    torch = _torch()
+    _check_volume(grad_out)
+    if grad_out.dtype != torch.float32:
+        raise HarpiaError(_lib.HARPIA_ERR_DTYPE, "grad_out must be float32")
+    gi = torch.empty_like(grad_out) if grad_in else None
+    gs = torch.zeros(3, dtype=torch.float64, device=grad_out.device) if grad_sigma else None
+    xc = _dtype_code(x) if x is not None else _lib.HARPIA_F32
+    e = _exec(grad_out, ex)
+    with _device_guard(grad_out):
+        _lib.check(_lib.load().harpia_gaussian3d_backward(
+            _ptr(x) if x is not None else None, xc, _ptr(grad_out), _ptr(gi) if gi is not None else None,
+            _lib.i64_3(grad_out.shape), _lib.f64_3(_triple(sigma, float)), _lib.i32_3(_triple(radius, int)),
+            gs.data_ptr() if gs is not None else None, e))
+    return gi, gs
+
+
+def morph_backward(x, grad_out, op: str, se: str = "box", radius=1, ex: Exec | None = None):
+    """Subgradient of erode/dilate(x): grad_out routed to the first extremum
+    (lexicographic (dz, dy, dx) order).  Device tensors; float32 gradients."""
+    torch = _torch()
+    _check_volume(x)
+    _check_volume(grad_out)
+    gi = torch.empty_like(grad_out)
+    code = {"erode": _lib.HARPIA_ERODE, "dilate": _lib.HARPIA_DILATE}[op]
+    sc = {"box": _lib.HARPIA_SE_BOX, "ball": _lib.HARPIA_SE_BALL}[se]
+    e = _exec(grad_out, ex)
+    with _device_guard(grad_out):
+        _lib.check(_lib.load().harpia_morph3d_backward(
+            _ptr(x), _dtype_code(x), _ptr(grad_out), _ptr(gi), _lib.i64_3(x.shape), code, sc,
+            _lib.i32_3(_triple(radius, int)), e))
+    return gi
+
+
+def _sigma_values(sigma):
+    torch = _torch()
+    if isinstance(sigma, torch.Tensor):
+        vals = sigma.detach().double().cpu().reshape(-1).tolist()
+        return (vals[0],) * 3 if len(vals) == 1 else tuple(vals)
+    return _triple(sigma, float)
+
+
+def _sigma_grad(sigma, gs):
+    """dL/d sigma in the shape of `sigma`: an isotropic sigma gets the sum of
+    the three per-axis derivatives (chain rule)."""
+    if gs is None:
+        return None
+    if sigma.numel() == 1:
+        return gs.sum().to(sigma.dtype).reshape(sigma.shape)
+    return gs.to(sigma.dtype).reshape(sigma.shape)
+
+
+def _autograd_base():
+    return _torch().autograd.Function
+
+
+class _LazyFunction(type):
+    """Builds the torch.autograd.Function subclass on first use, so that the
+    package imports without torch's autograd machinery being touched."""
+
+    def __getattr__(cls, name):
+        return getattr(cls._impl(), name)
+
+
+class GaussianFn(metaclass=_LazyFunction):
+    """y = G_sigma x as an autograd Function: GaussianFn.apply(x, sigma,
+    truncate).  sigma: float, triple, or a (learnable) tensor with 1 or 3
+    elements.  The radius is resolved from sigma in forward and held fixed
+    in backward; only x is saved."""
+    _cls = None
+
+    @classmethod
+    def _impl(cls):
+        if cls._cls is None:
+            torch = _torch()
+
+            class _Fn(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, x, sigma, truncate=3.0):
+                    s = _sigma_values(sigma)
+                    r = tuple(gauss_radius(t, truncate) for t in s)
+                    ctx.save_for_backward(x, sigma if isinstance(sigma, torch.Tensor) else None)
+                    ctx.s, ctx.r = s, r
+                    return gaussian(x.detach().contiguous(), s, truncate)
+
+                @staticmethod
+                def backward(ctx, gy):
+                    x, sig = ctx.saved_tensors
+                    need_s = sig is not None and ctx.needs_input_grad[1]
+                    gx, gs = gaussian_backward(x.contiguous(), gy.contiguous().float(), ctx.s, ctx.r,
+                                               grad_in=ctx.needs_input_grad[0], grad_sigma=need_s)
+                    return (gx.to(x.dtype) if gx is not None else None,
+                            _sigma_grad(sig, gs) if need_s else None, None)
+
+            cls._cls = _Fn
+        return cls._cls
+
+
+class MorphFn(metaclass=_LazyFunction):
+    """Erosion / dilation as an autograd Function: MorphFn.apply(x, op, se,
+    radius) with op 'erode' or 'dilate'; the gradient routes to the first
+    extremum.  Saves x only."""
+    _cls = None
+
+    @classmethod
+    def _impl(cls):
+        if cls._cls is None:
+            torch = _torch()
+
+            class _Fn(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, x, op, se="box", radius=1):
+                    ctx.save_for_backward(x)
+                    ctx.args = (op, se, radius)
+                    f = erode if op == "erode" else dilate
+                    return f(x.detach().contiguous(), se, radius)
+
+                @staticmethod
+                def backward(ctx, gy):
+                    (x,) = ctx.saved_tensors
+                    op, se, radius = ctx.args
+                    return morph_backward(x.contiguous(), gy.contiguous().float(), op, se, radius), None, None, None
+
+            cls._cls = _Fn
+        return cls._cls
+
+
+class GaussDilateFn(metaclass=_LazyFunction):
+    """d = dilate_se(G_sigma x) in one autograd node that stores only x and
+    sigma: backward recomputes y = G_sigma x, routes the upstream gradient
+    through the dilation's first maxima, then applies the Gaussian's adjoint
+    and sigma-gradient.  GaussDilateFn.apply(x, sigma, se, radius, truncate)."""
+    _cls = None
+
+    @classmethod
+    def _impl(cls):
+        if cls._cls is None:
+            torch = _torch()
+
+            class _Fn(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, x, sigma, se="box", radius=2, truncate=3.0):
+                    s = _sigma_values(sigma)
+                    r = tuple(gauss_radius(t, truncate) for t in s)
+                    ctx.save_for_backward(x, sigma if isinstance(sigma, torch.Tensor) else None)
+                    ctx.s, ctx.r, ctx.m, ctx.t = s, r, (se, radius), truncate
+                    y = gaussian(x.detach().contiguous(), s, truncate)
+                    return dilate(y, se, radius)
+
+                @staticmethod
+                def backward(ctx, gd):
+                    x, sig = ctx.saved_tensors
+                    se, radius = ctx.m
+                    y = gaussian(x.contiguous(), ctx.s, ctx.t)  # recomputed, not stored
+                    gy = morph_backward(y, gd.contiguous().float(), "dilate", se, radius)
+                    del y
+                    need_s = sig is not None and ctx.needs_input_grad[1]
+                    gx, gs = gaussian_backward(x.contiguous(), gy, ctx.s, ctx.r,
+                                               grad_in=ctx.needs_input_grad[0], grad_sigma=need_s)
+                    return (gx.to(x.dtype) if gx is not None else None,
+                            _sigma_grad(sig, gs) if need_s else None, None, None, None)
+
+            cls._cls = _Fn
+        return cls._cls
 
 
 import ctypes as _ctypes  # noqa: E402

@@ -87,6 +87,10 @@ SIGNATURES = {
     "harpia_morph3d": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _I64_3, ctypes.POINTER(ctypes.c_int),
                                       ctypes.c_int32, ctypes.c_int, _I32_3, ctypes.c_double,
                                       ctypes.c_int, _ex]),
+    "harpia_gaussian3d_backward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _I64_3, _F64_3, _I32_3,
+                                                  _vp, _ex]),
+    "harpia_morph3d_backward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _I64_3, ctypes.c_int,
+                                               ctypes.c_int, _I32_3, _ex]),
 }
 
 _lib = None

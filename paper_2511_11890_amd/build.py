@@ -37,17 +37,33 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _headers_mtime():
-    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
-    hs.append(os.path.join(INCLUDE, "harpia.h"))
-    return max(os.path.getmtime(h) for h in hs)
+_INC = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
+
+
+def _deps(path, seen=None):
+    """The file and every quoted include it pulls in, transitively."""
+    seen = set() if seen is None else seen
+    if path in seen:
+        return seen
+    seen.add(path)
+    for name in _INC.findall(open(path).read()):
+        for d in (os.path.dirname(path), CSRC, INCLUDE):
+            cand = os.path.join(d, name)
+            if os.path.exists(cand):
+                _deps(cand, seen)
+                break
+    return seen
+
+
+def _headers_mtime(src):
+    return max(os.path.getmtime(h) for h in _deps(src))
 
 
 def _compile(src: str, force: bool):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     log = obj + ".log"
     if (not force and os.path.exists(obj)
-            and os.path.getmtime(obj) >= max(os.path.getmtime(src), _headers_mtime())):
+            and os.path.getmtime(obj) >= _headers_mtime(src)):
         return obj, open(log).read() if os.path.exists(log) else ""
     cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
     p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)

@@ -317,4 +317,139 @@ harpia_status harpia_erode_dilate3d(const void *in, void *out_erode, void *out_d
     });
 }
 
+
+static Region whole_region(const void *p, const int64_t *n)
+{
+    Region r;
+    r.ptr = const_cast<void *>(p);
+    r.sy = n[2];
+    r.sz = n[1] * n[2];
+    for (int a = 0; a < 3; ++a) {
+        r.o[a] = 0;
+        r.e[a] = n[a];
+    }
+    return r;
+}
+
+harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t, const void *grad_out, void *grad_in,
+                                         const int64_t shape[3], const double sigma[3], const int32_t radius[3],
+                                         double *grad_sigma, const harpia_exec *ex)
+{
+    return guarded([&] {
+        check_shape(shape);
+        check_exec(ex);
+        if (!grad_out) fail(HARPIA_ERR_ARG, "grad_out is NULL");
+        if (!sigma || !radius) fail(HARPIA_ERR_ARG, "sigma / radius is NULL");
+        for (int a = 0; a < 3; ++a) {
+            if (!(sigma[a] > 0.0) || !std::isfinite(sigma[a])) fail(HARPIA_ERR_ARG, "sigma must be finite and > 0");
+            if (radius[a] < 0 || radius[a] > kMaxGaussRadius)
+                fail(HARPIA_ERR_ARG, "radius must be in [0, " + std::to_string(kMaxGaussRadius) + "]");
+        }
+        if (grad_sigma && !x) fail(HARPIA_ERR_ARG, "x is NULL (needed for grad_sigma)");
+        if (grad_sigma && !valid_dtype(x_t)) fail(HARPIA_ERR_DTYPE, "unsupported dtype");
+        if (!grad_in && !grad_sigma) return;
+        const int64_t nv = voxels(shape);
+        if (grad_in) check_alias(grad_out, nv * 4, grad_in, nv * 4);
+        if (grad_in && x) check_alias(x, nv * dtype_size(x_t), grad_in, nv * 4);
+        reset_alloc_counter();
+        if (!is_device_pointer(grad_out) || (grad_in && !is_device_pointer(grad_in)) ||
+            (grad_sigma && !is_device_pointer(x)))
+            fail(HARPIA_ERR_UNSUPPORTED, "the backward runs on device-resident volumes");
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        const int r[3] = {radius[0], radius[1], radius[2]};
+        const Region g_reg = whole_region(grad_out, shape);
+        bool allocated = false;
+        DevBuf scratch, partials, dsig, dvol;
+        if (grad_in) {
+            // adjoint of the reflect-boundary Gaussian = the same Gaussian
+            GaussTaps taps;
+            make_gauss_taps_r(sigma, r, taps);
+            const ChunkArgs a = make_chunk_args(g_reg, whole_region(grad_in, shape), shape);
+            const size_t need = gaussian_scratch_bytes(shape, r);
+            if (need) {
+                scratch.alloc(need);
+                allocated = true;
+            }
+            if (!launch_gaussian(a, HARPIA_F32, HARPIA_F32, taps, s, scratch.p, need))
+                fail(HARPIA_ERR_UNSUPPORTED, "no Gaussian kernel for these radii");
+            check_hip(hipGetLastError(), "kernel launch");
+        }
+        if (grad_sigma) {
+            const bool dev_out = is_device_pointer(grad_sigma);
+            double *dst = grad_sigma;
+            if (!dev_out) {
+                dsig.alloc(3 * sizeof(double));
+                dst = static_cast<double *>(dsig.p);
+            }
+            const Region x_reg = whole_region(x, shape);
+            for (int axis = 0; axis < 3; ++axis) {
+                GaussTaps dt;
+                make_gauss_dtaps_r(sigma, r, axis, dt);
+                const ChunkArgs a = make_chunk_args(x_reg, g_reg, shape);
+                int64_t nb;
+                if (gauss_fused_ok(dt, a)) {
+                    nb = gauss_dot_blocks(a, dt);
+                    if (!partials.p) partials.alloc((size_t)nb * sizeof(float));
+                    if (launch_gauss_dot(a, x_t, dt, s, static_cast<float *>(partials.p)) != nb)
+                        fail(HARPIA_ERR_UNSUPPORTED, "no fused kernel for these radii");
+                } else {
+                    // unfused: the derivative volume, then its dot with g
+                    if (!dvol.p) {
+                        dvol.alloc((size_t)nv * sizeof(float));
+                        const size_t need = gaussian_scratch_bytes(shape, r);
+                        if (need && !scratch.p) scratch.alloc(need);
+                    }
+                    const Region d_reg = whole_region(dvol.p, shape);
+                    const ChunkArgs ad = make_chunk_args(x_reg, d_reg, shape);
+                    if (!launch_gaussian(ad, x_t, HARPIA_F32, dt, s, scratch.p, gaussian_scratch_bytes(shape, r)))
+                        fail(HARPIA_ERR_UNSUPPORTED, "no Gaussian kernel for these radii");
+                    const int64_t max_blocks = 4096;
+                    if (!partials.p) partials.alloc((size_t)max_blocks * sizeof(float));
+                    nb = launch_dot_partials(d_reg, g_reg, static_cast<float *>(partials.p), max_blocks, s);
+                }
+                check_hip(hipGetLastError(), "kernel launch");
+                launch_reduce_f64(static_cast<const float *>(partials.p), nb, dst + axis, false, s);
+                check_hip(hipGetLastError(), "kernel launch");
+            }
+            if (!dev_out)
+                check_hip(hipMemcpyAsync(grad_sigma, dst, 3 * sizeof(double), hipMemcpyDeviceToHost, s),
+                          "hipMemcpyAsync");
+            allocated = true;
+        }
+        if (allocated) check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    });
+}
+
+harpia_status harpia_morph3d_backward(const void *in, harpia_dtype t, const void *grad_out, void *grad_in,
+                                      const int64_t shape[3], harpia_morph_op op, harpia_se se,
+                                      const int32_t radius[3], const harpia_exec *ex)
+{
+    return guarded([&] {
+        if (!in || !grad_out || !grad_in) fail(HARPIA_ERR_ARG, "in / grad_out / grad_in is NULL");
+        check_shape(shape);
+        check_exec(ex);
+        if (op != HARPIA_ERODE && op != HARPIA_DILATE) fail(HARPIA_ERR_ARG, "unknown morphology op");
+        const MorphArgs m = check_morph(t, se, radius, std::nan(""), HARPIA_BORDER_REFLECT, nullptr);
+        if (!morph_grad_supported(m.r)) fail(HARPIA_ERR_UNSUPPORTED, "morphology gradient radius above 8");
+        const int64_t nv = voxels(shape);
+        check_alias(grad_out, nv * 4, grad_in, nv * 4);
+        check_alias(in, nv * dtype_size(t), grad_in, nv * 4);
+        reset_alloc_counter();
+        if (!is_device_pointer(in) || !is_device_pointer(grad_out) || !is_device_pointer(grad_in))
+            fail(HARPIA_ERR_UNSUPPORTED, "the backward runs on device-resident volumes");
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        DevBuf code;
+        code.alloc((size_t)nv * sizeof(uint16_t));
+        const ChunkArgs a1 = make_chunk_args(whole_region(in, shape), whole_region(code.p, shape), shape);
+        if (!launch_argext(a1, t, (int)op, (int)se, m.r, static_cast<uint16_t *>(code.p), s))
+            fail(HARPIA_ERR_UNSUPPORTED, "no argext kernel");
+        check_hip(hipGetLastError(), "kernel launch");
+        const ChunkArgs a2 = make_chunk_args(whole_region(grad_out, shape), whole_region(grad_in, shape), shape);
+        if (!launch_gather(a2, static_cast<const uint16_t *>(code.p), (int)se, m.r, s))
+            fail(HARPIA_ERR_UNSUPPORTED, "no gather kernel");
+        check_hip(hipGetLastError(), "kernel launch");
+        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    });
+}
+
 }  // extern "C"

@@ -151,6 +151,9 @@ struct GaussTaps {
 // Fills taps in FP64 and rounds them to FP32 (host).
 void make_gauss_taps(const double sigma[3], double truncate, GaussTaps &t);
 void make_gauss_taps_r(const double sigma[3], const int radius[3], GaussTaps &t);
+// As make_gauss_taps_r, with axis `d_axis` replaced by d w / d sigma (radius
+// held fixed): w_k (k^2 - sum_j w_j j^2) / sigma^3, in FP64.
+void make_gauss_dtaps_r(const double sigma[3], const int radius[3], int d_axis, GaussTaps &t);
 
 // Launch the Gaussian on one chunk.  Returns false if no kernel handles the
 // dtype pair / radius combination (caller reports UNSUPPORTED).
@@ -176,5 +179,25 @@ bool launch_morph(const ChunkArgs &a, harpia_dtype t, const MorphSpec &m, hipStr
 bool launch_morph_ex(const ChunkArgs &a, harpia_dtype t, const MorphSpec &m, bool both, const Region *out2,
                      hipStream_t s);
 float compare_threshold(harpia_dtype t, double thr);
+
+// ---------------------------------------------------------- adjoints
+
+// Per-block partials of sum g * (G x) (g = a.out, float, output-region
+// layout) with the fused kernel; returns the partial count or -1 if the
+// taps / dtype need the unfused path.
+int64_t launch_gauss_dot(const ChunkArgs &a, harpia_dtype in_t, const GaussTaps &taps, hipStream_t s,
+                         float *partials);
+int64_t gauss_dot_blocks(const ChunkArgs &a, const GaussTaps &taps);
+bool gauss_fused_ok(const GaussTaps &taps, const ChunkArgs &a);
+// sum of partials[0..n) in FP64, fixed order, into out[0] (or added to it).
+void launch_reduce_f64(const float *partials, int64_t n, double *out, bool accumulate, hipStream_t s);
+// Per-block partials of sum a * b over a region; returns the block count.
+int64_t launch_dot_partials(const Region &a, const Region &b, float *partials, int64_t max_blocks, hipStream_t s);
+// Erosion / dilation subgradient: codes of the first extremum, then the
+// gather of the upstream gradient.  Radii up to 8 per axis.
+bool morph_grad_supported(const int r[3]);
+bool launch_argext(const ChunkArgs &a, harpia_dtype t, int op, int se, const int r[3], uint16_t *code,
+                   hipStream_t s);
+bool launch_gather(const ChunkArgs &a, const uint16_t *code, int se, const int r[3], hipStream_t s);
 
 }  // namespace harpia

@@ -43,6 +43,8 @@ void tail_halo(const std::vector<Stage> &st, size_t k, int64_t h[3])
 
 thread_local int t_alloc_count = 0;
 
+}  // namespace
+
 bool injected_failure()
 {
     const char *env = std::getenv("HARPIA_TEST_FAIL_ALLOC_AT");
@@ -51,26 +53,20 @@ bool injected_failure()
     return at > 0 && ++t_alloc_count == at;
 }
 
-struct DevBuf {
-    void *p = nullptr;
-    DevBuf() = default;
-    DevBuf(const DevBuf &) = delete;
-    DevBuf &operator=(const DevBuf &) = delete;
-    ~DevBuf()
-    {
-        if (p) (void)hipFree(p);
+void DevBuf::alloc(size_t bytes)
+{
+    if (bytes == 0) return;
+    if (injected_failure()) fail(HARPIA_ERR_OOM, "device allocation failed (injected)");
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        fail(HARPIA_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
-    void alloc(size_t bytes)
-    {
-        if (bytes == 0) return;
-        if (injected_failure()) fail(HARPIA_ERR_OOM, "device allocation failed (injected)");
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            fail(HARPIA_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-        }
-    }
-};
+}
+
+bool is_device_pointer(const void *ptr);
+
+namespace {
 
 struct PinBuf {
     void *p = nullptr;
@@ -116,6 +112,12 @@ struct EventH {
 };
 
 enum class Mem { Device, Pinned, Pageable };
+
+}  // namespace
+
+bool is_device_pointer(const void *ptr);
+
+namespace {
 
 Mem classify(const void *p)
 {
@@ -676,6 +678,10 @@ size_t resolve_budget(const harpia_exec *ex, bool need_device)
     check_hip(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
     return (size_t)((double)free_b * frac);
 }
+
+bool is_device_pointer(const void *ptr) { return classify(ptr) == Mem::Device; }
+
+void reset_alloc_counter() { t_alloc_count = 0; }
 
 void run_job(const Job &job)
 {

@@ -49,6 +49,23 @@ void plan_chunks(const int64_t n[3], const int32_t halo[3], const int64_t chunk[
 // (bytes), HARPIA_BUDGET_FRACTION.
 size_t resolve_budget(const harpia_exec *ex, bool need_device);
 
+// Device memory owned for the duration of one call (freed by the
+// destructor).  alloc() honours the HARPIA_TEST_FAIL_ALLOC_AT test hook.
+struct DevBuf {
+    void *p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    void alloc(size_t bytes);
+};
+
+bool is_device_pointer(const void *ptr);
+void reset_alloc_counter();
+
 // Run a job: resident on the caller's stream when `in`/`out` are device
 // pointers, streamed chunk by chunk when they are host pointers.
 void run_job(const Job &job);

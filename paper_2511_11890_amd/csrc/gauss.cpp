@@ -26,11 +26,14 @@
 #include <cmath>
 
 #include "common.h"
+#include "gauss_grid.h"
 
 namespace harpia {
 
 template <typename Tin, typename Tout>
 bool gauss_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes);
+template <typename Tin>
+int64_t gauss_dot_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials);
 
 size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3])
 {
@@ -55,11 +58,47 @@ void make_gauss_taps_r(const double sigma[3], const int radius[3], GaussTaps &t)
     }
 }
 
+void make_gauss_dtaps_r(const double sigma[3], const int radius[3], int d_axis, GaussTaps &t)
+{
+    make_gauss_taps_r(sigma, radius, t);
+    const int r = radius[d_axis];
+    const double sg = sigma[d_axis];
+    double e[kMaxGaussRadius + 1];
+    double total = 0.0, m2 = 0.0;
+    for (int k = 0; k <= r; ++k) {
+        e[k] = std::exp(-((double)k * (double)k) / (2.0 * sg * sg));
+        total += (k == 0) ? e[k] : 2.0 * e[k];
+    }
+    for (int k = 1; k <= r; ++k) m2 += 2.0 * (e[k] / total) * (double)k * (double)k;
+    for (int k = 0; k <= kMaxGaussRadius; ++k)
+        t.w[d_axis][k] = (k <= r) ? (float)((e[k] / total) * ((double)k * k - m2) / (sg * sg * sg)) : 0.f;
+}
+
 void make_gauss_taps(const double sigma[3], double truncate, GaussTaps &t)
 {
     int r[3];
     for (int ax = 0; ax < 3; ++ax) r[ax] = (int)(truncate * sigma[ax] + 0.5);
     make_gauss_taps_r(sigma, r, t);
+}
+
+bool gauss_fused_ok(const GaussTaps &taps, const ChunkArgs &a) { return gauss_detail::fused_ok(taps, a); }
+
+int64_t gauss_dot_blocks(const ChunkArgs &a, const GaussTaps &taps)
+{
+    return gauss_detail::fused_grid(a, taps.r[0]).blocks;
+}
+
+int64_t launch_gauss_dot(const ChunkArgs &a, harpia_dtype in_t, const GaussTaps &taps, hipStream_t s,
+                         float *partials)
+{
+    switch (in_t) {
+    case HARPIA_F32: return gauss_dot_run<float>(a, taps, s, partials);
+    case HARPIA_U16: return gauss_dot_run<uint16_t>(a, taps, s, partials);
+    case HARPIA_U8: return gauss_dot_run<uint8_t>(a, taps, s, partials);
+    case HARPIA_F16: return gauss_dot_run<_Float16>(a, taps, s, partials);
+    case HARPIA_BF16: return gauss_dot_run<bf16_t>(a, taps, s, partials);
+    }
+    return -1;
 }
 
 bool launch_gaussian(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t, const GaussTaps &taps,

@@ -3,4 +3,5 @@
 
 namespace harpia {
 template bool gauss_run<bf16_t, bf16_t>(const ChunkArgs &, const GaussTaps &, hipStream_t, void *, size_t);
+template int64_t gauss_dot_run<bf16_t>(const ChunkArgs &, const GaussTaps &, hipStream_t, float *);
 }  // namespace harpia

@@ -3,4 +3,5 @@
 
 namespace harpia {
 template bool gauss_run<_Float16, _Float16>(const ChunkArgs &, const GaussTaps &, hipStream_t, void *, size_t);
+template int64_t gauss_dot_run<_Float16>(const ChunkArgs &, const GaussTaps &, hipStream_t, float *);
 }  // namespace harpia

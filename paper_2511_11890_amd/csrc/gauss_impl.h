@@ -30,6 +30,7 @@
 #include <utility>
 
 #include "common.h"
+#include "gauss_grid.h"
 
 namespace harpia {
 
@@ -49,8 +50,6 @@ __device__ __forceinline__ void static_for(F &&f)
 namespace gauss_detail {
 
 
-constexpr int kTX = 64;   // tile columns (x)
-constexpr int kTY = 16;   // tile rows (y)
 constexpr int kNT = 256;  // threads per workgroup
 constexpr int kMY = 4;    // rows per y-pass work item
 
@@ -87,9 +86,42 @@ __device__ __forceinline__ void store4(T *p, const float v[4], int nvalid)
         if (c < nvalid) p[c] = from_f32<T>(v[c]);
 }
 
-template <typename Tin, typename Tout, int R>
-__global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps taps, int zlen,
-                                                          int tiles_x, int tiles_y)
+// Slices of input kept in flight per thread (the prefetch ring depth): deep
+// enough that the loads issued for slice i + D cover the HBM latency while
+// slices i .. i + D - 1 are filtered, shallow enough to keep occupancy.
+constexpr int gauss_prefetch_depth(int R) { return R <= 4 ? 3 : (R <= 8 ? 2 : 1); }
+
+// Output policies of the fused tile.  put(off, nvalid, v) receives the 4
+// finished outputs of one thread at element offset `off` of the output
+// region (a.out layout); nvalid of them lie inside the region.
+template <typename Tout>
+struct StoreOut {
+    Tout *base;
+    __device__ __forceinline__ void put(int64_t off, int nvalid, const float v[4])
+    {
+        if (nvalid > 0) store4(base + off, v, nvalid);
+    }
+};
+
+// Accumulates sum over outputs of g[o] * filtered[o] (g laid out like the
+// output region): with derivative taps on one axis this is one term of the
+// sigma-gradient.
+struct DotOut {
+    const float *g;
+    float sum;
+    __device__ __forceinline__ void put(int64_t off, int nvalid, const float v[4])
+    {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < nvalid) sum = fmaf(g[off + c], v[c], sum);
+    }
+};
+
+// One tile of the fused Gaussian: output columns [x0, x0 + kTX) x
+// [y0, y0 + kTY) of the output region, slices [zo0, zo0 + zlen).
+template <typename Tin, int R, int D, class Out>
+__device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &taps, int zlen, int bx, int by,
+                                           int bz, Out &out)
 {
     constexpr int P = 2 * R + 1;
     constexpr int PW = kTX + 2 * R;  // patch columns
@@ -100,16 +132,15 @@ __global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps
     constexpr int NYI = PW * (kTY / kMY);
     constexpr int NH = 4 + 2 * R;  // x-pass inputs per quad
     constexpr int NH4 = (NH + 3) / 4;
+    constexpr int QSZ = kTY * QP + 4 * NH4;
 
-    __shared__ float sP[PSZ];
-    __shared__ __attribute__((aligned(16))) float sQ[kTY * QP + 4 * NH4];
+    // Double-buffered: slice i is filtered in y from sP[i & 1] into
+    // sQ[i & 1] while slice i - 1 is filtered in x from sQ[(i - 1) & 1], so
+    // one barrier per slice separates the phases.
+    __shared__ float sP[2 * PSZ];
+    __shared__ __attribute__((aligned(16))) float sQ[2 * QSZ];
 
     const int tid = threadIdx.x;
-    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int bx = (int)(b % (uint32_t)tiles_x);
-    const int by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
-    const int bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
-
     const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
     const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1];
     const int64_t x0 = xbeg + (int64_t)bx * kTX;
@@ -148,13 +179,31 @@ __global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps
     }
 
     const Tin *in = static_cast<const Tin *>(a.in);
-    float pf[NLD];
-    auto fetch = [&](int64_t s) __attribute__((always_inline)) {
-        const int64_t zl = reflect_index(s, a.n[0]) - a.in_o[0];
+    const int64_t s0 = zo0 - R;
+    const int nsteps = (int)(zo1 - zo0) + 2 * R;  // input slices of this range
+
+    // Prefetch ring: at the start of step i, pf[k] holds slice i + 1 + k.
+    // It keeps the raw loaded values; converting them at load time would make
+    // the loads complete before the next slice is filtered.
+    Tin pf[D][NLD];
+    auto fetch = [&](int j, Tin(&dst)[NLD]) __attribute__((always_inline)) {
+        const int64_t zl = reflect_index(s0 + j, a.n[0]) - a.in_o[0];
         const Tin *base = in + zl * a.in_sz;
 #pragma unroll
-        for (int i = 0; i < NLD; ++i)
-            if (i < NLD - 1 || tid + i * kNT < PSZ) pf[i] = to_f32(base[off[i]]);
+        for (int k = 0; k < NLD; ++k)
+            if (k < NLD - 1 || tid + k * kNT < PSZ) dst[k] = base[off[k]];
+    };
+    auto stage_and_advance = [&](int j) __attribute__((always_inline)) {
+        // pf[0] holds slice j: store it, shift the ring, fetch slice j + D
+        float *dst = sP + (j & 1) * PSZ;
+#pragma unroll
+        for (int k = 0; k < NLD; ++k)
+            if (k < NLD - 1 || tid + k * kNT < PSZ) dst[tid + k * kNT] = to_f32(pf[0][k]);
+#pragma unroll
+        for (int d = 0; d + 1 < D; ++d)
+#pragma unroll
+            for (int k = 0; k < NLD; ++k) pf[d][k] = pf[d + 1][k];
+        if (j + D < nsteps) fetch(j + D, pf[D - 1]);
     };
 
     const int qrow = tid / (kTX / 4);
@@ -162,7 +211,7 @@ __global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps
     const int64_t gy_out = y0 + qrow;
     const int64_t gx_out = x0 + qcol;
     const int nvalid = (gy_out < yend) ? (int)min((int64_t)4, xend - gx_out) : 0;
-    Tout *outp = static_cast<Tout *>(a.out) + (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
+    const int64_t col_off = (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
 
     float acc[P][4];
 #pragma unroll
@@ -170,74 +219,123 @@ __global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[j][c] = 0.f;
 
-    const int64_t s0 = zo0 - R;
-    const int nsteps = (int)(zo1 - zo0) + 2 * R;
-    fetch(s0);
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        if (d < nsteps) fetch(d, pf[d]);
+    stage_and_advance(0);
+    __syncthreads();
 
-    for (int base = 0; base < nsteps; base += P) {
+    // Step i: x and z passes of slice i - 1, y pass of slice i, staging of
+    // slice i + 1.  Steps run 0 .. nsteps; the slot of output o in the z
+    // ring is (o - s0) mod P, and slice j feeds outputs j - R .. j + R.
+    for (int base = 0; base <= nsteps; base += P) {
         static_for<P>([&](auto U) {
             constexpr int u = decltype(U)::value;
             const int i = base + u;
-            if (i >= nsteps) return;
+            if (i > nsteps) return;
 
-            // 1. stage the slice, then start fetching the next one
+            if (i >= 1) {
+                // x pass of slice i - 1: 4 adjacent outputs from its y-pass row
+                const float *q = sQ + ((i - 1) & 1) * QSZ;
+                float h[NH4 * 4];
+                const float4 *q4 = reinterpret_cast<const float4 *>(q + qrow * QP + qcol);
 #pragma unroll
-            for (int k = 0; k < NLD; ++k)
-                if (k < NLD - 1 || tid + k * kNT < PSZ) sP[tid + k * kNT] = pf[k];
-            if (i + 1 < nsteps) fetch(s0 + i + 1);
-            __syncthreads();
-
-            // 2. y pass: sP (PH x PW) -> sQ (kTY x PW)
-            for (int it = tid; it < NYI; it += kNT) {
-                const int col = it % PW, rg = it / PW;
-                float v[kMY + 2 * R];
+                for (int j = 0; j < NH4; ++j) {
+                    const float4 t4 = q4[j];
+                    h[4 * j + 0] = t4.x;
+                    h[4 * j + 1] = t4.y;
+                    h[4 * j + 2] = t4.z;
+                    h[4 * j + 3] = t4.w;
+                }
+                float t[4];
 #pragma unroll
-                for (int j = 0; j < kMY + 2 * R; ++j) v[j] = sP[(rg * kMY + j) * PW + col];
+                for (int c = 0; c < 4; ++c) {
+                    float sacc = wx[0] * h[c + R];
 #pragma unroll
-                for (int m = 0; m < kMY; ++m) {
-                    float sacc = wy[0] * v[m + R];
+                    for (int k = 1; k <= R; ++k) sacc = fmaf(wx[k], h[c + R - k] + h[c + R + k], sacc);
+                    t[c] = sacc;
+                }
+                // z pass: slice j = i - 1 feeds output j + d with weight w|d|
+                static_for<P>([&](auto DD) {
+                    constexpr int d = decltype(DD)::value - R;
+                    constexpr int sl = (u - 1 + d + 2 * P) % P;
+                    const float wd = wz[d < 0 ? -d : d];
 #pragma unroll
-                    for (int k = 1; k <= R; ++k) sacc = fmaf(wy[k], v[m + R - k] + v[m + R + k], sacc);
-                    sQ[(rg * kMY + m) * QP + col] = sacc;
+                    for (int c = 0; c < 4; ++c) acc[sl][c] = (d == R) ? wd * t[c] : fmaf(wd, t[c], acc[sl][c]);
+                });
+                if (i - 1 >= 2 * R) {
+                    constexpr int sl = (u - 1 - R + 2 * P) % P;
+                    const int64_t o = s0 + (i - 1) - R;
+                    out.put(col_off + (o - a.out_o[0]) * a.out_sz, nvalid, acc[sl]);
                 }
             }
-            __syncthreads();
-
-            // 3. x pass: 4 adjacent outputs from sQ row qrow
-            float h[NH4 * 4];
-            const float4 *q4 = reinterpret_cast<const float4 *>(&sQ[qrow * QP + qcol]);
+            if (i < nsteps) {
+                // y pass of slice i: sP (PH x PW) -> sQ (kTY x PW)
+                const float *p = sP + (i & 1) * PSZ;
+                float *q = sQ + (i & 1) * QSZ;
+                for (int it = tid; it < NYI; it += kNT) {
+                    const int col = it % PW, rg = it / PW;
+                    float v[kMY + 2 * R];
 #pragma unroll
-            for (int j = 0; j < NH4; ++j) {
-                const float4 t4 = q4[j];
-                h[4 * j + 0] = t4.x;
-                h[4 * j + 1] = t4.y;
-                h[4 * j + 2] = t4.z;
-                h[4 * j + 3] = t4.w;
-            }
-            float t[4];
+                    for (int j = 0; j < kMY + 2 * R; ++j) v[j] = p[(rg * kMY + j) * PW + col];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                float sacc = wx[0] * h[c + R];
+                    for (int m = 0; m < kMY; ++m) {
+                        float sacc = wy[0] * v[m + R];
 #pragma unroll
-                for (int k = 1; k <= R; ++k) sacc = fmaf(wx[k], h[c + R - k] + h[c + R + k], sacc);
-                t[c] = sacc;
-            }
-
-            // 4. z pass: scatter into the ring; slot of output o is (o - s0) mod P
-            static_for<P>([&](auto D) {
-                constexpr int d = decltype(D)::value - R;
-                constexpr int sl = (u + d + 2 * P) % P;
-                const float wd = wz[d < 0 ? -d : d];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[sl][c] = (d == R) ? wd * t[c] : fmaf(wd, t[c], acc[sl][c]);
-            });
-            if (i >= 2 * R) {
-                constexpr int sl = (u - R + 2 * P) % P;
-                const int64_t o = s0 + i - R;
-                if (nvalid > 0) store4(outp + (o - a.out_o[0]) * a.out_sz, acc[sl], nvalid);
+                        for (int k = 1; k <= R; ++k) sacc = fmaf(wy[k], v[m + R - k] + v[m + R + k], sacc);
+                        q[(rg * kMY + m) * QP + col] = sacc;
+                    }
+                }
+                if (i + 1 < nsteps) stage_and_advance(i + 1);
+                __syncthreads();
             }
         });
     }
+}
+
+__device__ __forceinline__ void tile_of_block(uint32_t b, int tiles_x, int tiles_y, int &bx, int &by, int &bz)
+{
+    bx = (int)(b % (uint32_t)tiles_x);
+    by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
+    bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
+}
+
+template <typename Tin, typename Tout, int R, int D = gauss_prefetch_depth(R)>
+__global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps taps, int zlen, int tiles_x,
+                                                          int tiles_y)
+{
+    int bx, by, bz;
+    tile_of_block(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, bx, by, bz);
+    StoreOut<Tout> out{static_cast<Tout *>(a.out)};
+    gauss_tile<Tin, R, D>(a, taps, zlen, bx, by, bz, out);
+}
+
+// Sum of 256 values in a fixed order (wave butterflies, then the 4 wave
+// sums); the result is valid in thread 0.
+__device__ __forceinline__ float block_sum_256(float v)
+{
+    __shared__ float wsum[kNT / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+// sigma-gradient term: per-block FP32 partial of sum g * (G' x); a.out is
+// the upstream gradient g (float, laid out like the output region).
+template <typename Tin, int R, int D = gauss_prefetch_depth(R)>
+__global__ __launch_bounds__(kNT) void gauss_dot_kernel(ChunkArgs a, GaussTaps taps, int zlen, int tiles_x,
+                                                        int tiles_y, float *partials)
+{
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    int bx, by, bz;
+    tile_of_block(b, tiles_x, tiles_y, bx, by, bz);
+    DotOut out{static_cast<const float *>(a.out), 0.f};
+    gauss_tile<Tin, R, D>(a, taps, zlen, bx, by, bz, out);
+    const float t = block_sum_256(out.sum);
+    if (threadIdx.x == 0) partials[b] = t;
 }
 
 // One 1D pass along `axis` (0 z, 1 y, 2 x): dst = w * src, reflect along the
@@ -270,27 +368,43 @@ __global__ __launch_bounds__(256) void gauss_pass_kernel(const Tin *src, int64_t
 template <typename Tin, typename Tout, int R>
 void launch_fused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
-    const int tiles_x = (int)((a.out_e[2] + kTX - 1) / kTX);
-    const int tiles_y = (int)((a.out_e[1] + kTY - 1) / kTY);
-    const int64_t tiles = (int64_t)tiles_x * tiles_y;
-    // z range per workgroup: enough workgroups to fill the chip several
-    // times over, but long enough that the 2r-slice warm-up stays small.
-    int64_t zlen = a.out_e[0];
-    const int64_t want_blocks = 4096;
-    if (tiles * 1 < want_blocks) {
-        int64_t nzc = (want_blocks + tiles - 1) / tiles;
-        zlen = (a.out_e[0] + nzc - 1) / nzc;
-        const int64_t min_len = 8 * R > 32 ? 8 * R : 32;
-        if (zlen < min_len) zlen = min_len;
-    } else {
-        const int64_t max_len = 256;
-        if (zlen > max_len && tiles < 4 * want_blocks) zlen = max_len;
+    const FusedGrid g = fused_grid(a, R);
+    hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, taps,
+                       g.zlen, g.tiles_x, g.tiles_y);
+}
+
+template <typename Tin, int R>
+void launch_dot(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
+{
+    const FusedGrid g = fused_grid(a, R);
+    hipLaunchKernelGGL((gauss_dot_kernel<Tin, R>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, taps, g.zlen,
+                       g.tiles_x, g.tiles_y, partials);
+}
+
+template <typename Tin>
+bool dispatch_dot(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
+{
+    switch (r) {
+#define HARPIA_CASE(RR)                           \
+    case RR:                                      \
+        launch_dot<Tin, RR>(a, taps, s, partials); \
+        return true;
+        HARPIA_CASE(1)
+        HARPIA_CASE(2)
+        HARPIA_CASE(3)
+        HARPIA_CASE(4)
+        HARPIA_CASE(5)
+        HARPIA_CASE(6)
+        HARPIA_CASE(7)
+        HARPIA_CASE(8)
+        HARPIA_CASE(9)
+        HARPIA_CASE(10)
+        HARPIA_CASE(11)
+        HARPIA_CASE(12)
+#undef HARPIA_CASE
+    default:
+        return false;
     }
-    if (zlen > a.out_e[0]) zlen = a.out_e[0];
-    const int64_t zch = (a.out_e[0] + zlen - 1) / zlen;
-    const int64_t nb = tiles * zch;
-    hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R>), dim3((uint32_t)nb), dim3(kNT), 0, s, a, taps,
-                       (int)zlen, tiles_x, tiles_y);
 }
 
 template <typename Tin, typename Tout>
@@ -359,14 +473,6 @@ void launch_unfused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, fl
     launch_pass<float, Tout>(s2p, r2, static_cast<Tout *>(a.out), dst, 0, a.n[0], taps, s);
 }
 
-inline bool fused_ok(const GaussTaps &t, const ChunkArgs &a)
-{
-    if (!(t.r[0] == t.r[1] && t.r[1] == t.r[2])) return false;
-    if (t.r[0] < 1 || t.r[0] > kGaussFusedMaxR) return false;
-    // in-plane offsets are 32-bit
-    return a.in_sy * (a.n[1] + 1) < (int64_t)1 << 31;
-}
-
 template <typename Tin, typename Tout>
 bool run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes)
 {
@@ -383,6 +489,16 @@ template <typename Tin, typename Tout>
 bool gauss_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes)
 {
     return gauss_detail::run<Tin, Tout>(a, taps, s, scratch, scratch_bytes);
+}
+
+// Per-block partials of sum g * (G x) for the fused case (equal radii
+// 1..kGaussFusedMaxR).  Returns the number of partials written, or -1.
+template <typename Tin>
+int64_t gauss_dot_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
+{
+    if (!gauss_detail::fused_ok(taps, a)) return -1;
+    if (!gauss_detail::dispatch_dot<Tin>(taps.r[0], a, taps, s, partials)) return -1;
+    return gauss_detail::fused_grid(a, taps.r[0]).blocks;
 }
 
 }  // namespace harpia

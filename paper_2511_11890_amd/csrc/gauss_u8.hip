@@ -3,4 +3,5 @@
 
 namespace harpia {
 template bool gauss_run<uint8_t, float>(const ChunkArgs &, const GaussTaps &, hipStream_t, void *, size_t);
+template int64_t gauss_dot_run<uint8_t>(const ChunkArgs &, const GaussTaps &, hipStream_t, float *);
 }  // namespace harpia

@@ -54,6 +54,8 @@ namespace morph_detail {
 
 constexpr int kNT = 256;
 constexpr int kMaxFastR = 4;
+constexpr int kDepth = 3;     // input slices in flight per thread (prefetch ring)
+constexpr int kBinDepth = 1;  // binary: words are packed on load, so no ring
 
 constexpr int isqrt_c(int v)
 {
@@ -171,12 +173,14 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
     }
 
     const T *in = static_cast<const T *>(a.in);
-    float pf[NLD];
-    auto fetch = [&](int64_t s) __attribute__((always_inline)) {
+    // Prefetch ring: at the start of step i, pf[k] holds slice i + k, as
+    // raw loaded values (converted when staged, so the loads stay in flight).
+    T pf[kDepth][NLD];
+    auto fetch = [&](int64_t s, T(&dst)[NLD]) __attribute__((always_inline)) {
         const T *base = in + (reflect_index(s, a.n[0]) - a.in_o[0]) * a.in_sz;
 #pragma unroll
         for (int i = 0; i < NLD; ++i)
-            if (i < NLD - 1 || tid + i * kNT < PSZ) pf[i] = to_f32(base[off[i]]);
+            if (i < NLD - 1 || tid + i * kNT < PSZ) dst[i] = base[off[i]];
     };
 
     const int qrow = tid / (kGTX / 4);
@@ -197,7 +201,9 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
 
     const int64_t s0 = zo0 - R;
     const int nsteps = (int)(zo1 - zo0) + 2 * R;
-    fetch(s0);
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d)
+        if (d < nsteps) fetch(s0 + d, pf[d]);
 
     for (int base = 0; base < nsteps; base += P) {
         static_for<P>([&](auto U) {
@@ -205,11 +211,16 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
             const int i = base + u;
             if (i >= nsteps) return;
 
-            // 1. stage (with the sign flip of a single erosion)
+            // 1. stage (with the sign flip of a single erosion), advance the ring
 #pragma unroll
             for (int k = 0; k < NLD; ++k)
-                if (k < NLD - 1 || tid + k * kNT < PSZ) sP[lds[k]] = BOTH ? pf[k] : sign * pf[k];
-            if (i + 1 < nsteps) fetch(s0 + i + 1);
+                if (k < NLD - 1 || tid + k * kNT < PSZ)
+                    sP[lds[k]] = BOTH ? to_f32(pf[0][k]) : sign * to_f32(pf[0][k]);
+#pragma unroll
+            for (int d = 0; d + 1 < kDepth; ++d)
+#pragma unroll
+                for (int k = 0; k < NLD; ++k) pf[d][k] = pf[d + 1][k];
+            if (i + kDepth < nsteps) fetch(s0 + i + kDepth, pf[kDepth - 1]);
             __syncthreads();
 
             // 2. stage A: x-run extrema of every level on all patch rows
@@ -252,8 +263,10 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
             }
             __syncthreads();
 
-            // 3. stage B: in-plane disc of every z-class, 4 columns
-            float D[NM][S::NC][4];
+            // 3. stage B: in-plane disc of each z-class (4 columns), fed
+            // straight into the z ring slots of the offsets of that class
+            // (each slot takes one contribution per slice, so the order of
+            // the classes does not matter; slot (u + R) takes its first).
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
                 static_for<S::NC>([&](auto C) {
@@ -272,23 +285,18 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
                             else dv[q] = (m == 0) ? fmaxf(dv[q], tv[q]) : fminf(dv[q], tv[q]);
                         }
                     });
+                    // 4. z ring: offsets d with class c
+                    static_for<P>([&](auto DD) {
+                        constexpr int d = decltype(DD)::value - R;
+                        if constexpr (S::cls(d) == c) {
+                            constexpr int sl = (u + d + 2 * P) % P;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) D[m][c][q] = dv[q];
-                });
-            }
-
-            // 4. z ring
-#pragma unroll
-            for (int m = 0; m < NM; ++m) {
-                static_for<P>([&](auto DD) {
-                    constexpr int d = decltype(DD)::value - R;
-                    constexpr int sl = (u + d + 2 * P) % P;
-                    constexpr int c = S::cls(d);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        acc[m][sl][q] = (d == R) ? D[m][c][q]
-                                                 : ((m == 0) ? fmaxf(acc[m][sl][q], D[m][c][q])
-                                                             : fminf(acc[m][sl][q], D[m][c][q]));
+                            for (int q = 0; q < 4; ++q)
+                                acc[m][sl][q] = (d == R) ? dv[q]
+                                                         : ((m == 0) ? fmaxf(acc[m][sl][q], dv[q])
+                                                                     : fminf(acc[m][sl][q], dv[q]));
+                        }
+                    });
                 });
             }
             if (i >= 2 * R && nvalid > 0) {
@@ -401,8 +409,9 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
     }
 
     const Tin *in = static_cast<const Tin *>(a.in);
-    uint32_t pf[NLW];
-    auto fetch = [&](int64_t s) __attribute__((always_inline)) {
+    // Prefetch ring: at the start of step i, pf[k] holds slice i + k.
+    uint32_t pf[kBinDepth][NLW];
+    auto fetch = [&](int64_t s, uint32_t(&dst)[NLW]) __attribute__((always_inline)) {
         const Tin *base = in + (reflect_index(s, a.n[0]) - a.in_o[0]) * a.in_sz;
 #pragma unroll
         for (int i = 0; i < NLW; ++i) {
@@ -424,7 +433,7 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
                         wv |= binarise(base[ly * a.in_sy + lx], thr, use_thr) << (8 * j);
                     }
                 }
-                pf[i] = wv;
+                dst[i] = wv;
             }
         }
     };
@@ -447,7 +456,9 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
 
     const int64_t s0 = zo0 - R;
     const int nsteps = (int)(zo1 - zo0) + 2 * R;
-    fetch(s0);
+#pragma unroll
+    for (int d = 0; d < kBinDepth; ++d)
+        if (d < nsteps) fetch(s0 + d, pf[d]);
 
     for (int base = 0; base < nsteps; base += P) {
         static_for<P>([&](auto U) {
@@ -457,8 +468,12 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
 
 #pragma unroll
             for (int k = 0; k < NLW; ++k)
-                if (k < NLW - 1 || tid + k * kNT < NWI) sP[tid + k * kNT] = BOTH ? pf[k] : (pf[k] ^ fmask);
-            if (i + 1 < nsteps) fetch(s0 + i + 1);
+                if (k < NLW - 1 || tid + k * kNT < NWI) sP[tid + k * kNT] = BOTH ? pf[0][k] : (pf[0][k] ^ fmask);
+#pragma unroll
+            for (int d = 0; d + 1 < kBinDepth; ++d)
+#pragma unroll
+                for (int k = 0; k < NLW; ++k) pf[d][k] = pf[d + 1][k];
+            if (i + kBinDepth < nsteps) fetch(s0 + i + kBinDepth, pf[kBinDepth - 1]);
             __syncthreads();
 
             // stage A: word-level x runs (OR for m = 0, AND for m = 1)
@@ -483,7 +498,6 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
             }
             __syncthreads();
 
-            uint32_t D[NM][S::NC][4];
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
                 static_for<S::NC>([&](auto C) {
@@ -501,22 +515,17 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
                             else dv[q] = (m == 0) ? (dv[q] | tv[q]) : (dv[q] & tv[q]);
                         }
                     });
+                    static_for<P>([&](auto DD) {
+                        constexpr int d = decltype(DD)::value - R;
+                        if constexpr (S::cls(d) == c) {
+                            constexpr int sl = (u + d + 2 * P) % P;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) D[m][c][q] = dv[q];
-                });
-            }
-
-#pragma unroll
-            for (int m = 0; m < NM; ++m) {
-                static_for<P>([&](auto DD) {
-                    constexpr int d = decltype(DD)::value - R;
-                    constexpr int sl = (u + d + 2 * P) % P;
-                    constexpr int c = S::cls(d);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        acc[m][sl][q] = (d == R) ? D[m][c][q]
-                                                 : ((m == 0) ? (acc[m][sl][q] | D[m][c][q])
-                                                             : (acc[m][sl][q] & D[m][c][q]));
+                            for (int q = 0; q < 4; ++q)
+                                acc[m][sl][q] = (d == R) ? dv[q]
+                                                         : ((m == 0) ? (acc[m][sl][q] | dv[q])
+                                                                     : (acc[m][sl][q] & dv[q]));
+                        }
+                    });
                 });
             }
             if (i >= 2 * R && nvalid > 0) {
