@@ -110,6 +110,11 @@ def run_resident(args):
             h._lib.HARPIA_SE_BALL, h._lib.i32_3((3, 3, 3)), float("nan"), 0,
             h._lib.make_exec(stream=torch.cuda.current_stream().cuda_stream)))
 
+    if args.copy_ref:
+        # a plain device copy of the same volume (reference for HBM counters)
+        ero.copy_(v)
+        torch.cuda.synchronize()
+
     ops = [("gauss_s1", lambda: op_gauss(1.0), 3), ("gauss_s2", lambda: op_gauss(2.0), 6),
            ("gauss_s4", lambda: op_gauss(4.0), 12), ("erode_dilate_ball3", op_morph, 3)]
     outputs_per_step = 5
@@ -118,6 +123,17 @@ def run_resident(args):
         for _, fn, _ in ops:
             fn()
     torch.cuda.synchronize()
+
+    # achievable HBM ceiling on this device: a plain device-to-device copy of
+    # the volume (read + write bytes), timed the same way
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ero.copy_(v)
+    c0.record()
+    for _ in range(5):
+        ero.copy_(v)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 4 * vox * 5 / c0.elapsed_time(c1) / 1e6
 
     events = {name: [] for name, _, _ in ops}
     t0 = time.perf_counter()
@@ -173,7 +189,7 @@ def run_resident(args):
             "config": {"workload": "resident %d^3 float32 porous phantom: Gaussian sigma 1,2,4 + "
                                    "grayscale erode+dilate ball r=3" % n, "voxels": vox,
                        "outputs_per_step": outputs_per_step},
-            "roofline": roof, "ops": per_op}
+            "roofline": roof, "ops": per_op, "hbm_copy_gbs": round(copy_gbs, 1)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(v)
     return line
@@ -265,6 +281,8 @@ def main():
     ap.add_argument("--workload", default="resident", choices=["resident", "precision", "chunked"])
     ap.add_argument("--size", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run one plain device copy of the volume (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs no multi-GPU path (one process, one device). "

@@ -249,6 +249,67 @@ harpia_status harpia_morph3d_backward(const void *in, harpia_dtype t,
                                       const int32_t radius[3],
                                       const harpia_exec *ex);
 
+/* ------------------------------------------------------------------
+ * Batched crops (an extension beyond the paper: many uneven volumes, e.g.
+ * training crops or the edge chunks of a volume, in one persistent launch).
+ * Each launch takes up to 32 crops whose (crop, tile) work items are strided
+ * over the resident workgroups; larger batches are split into launches of
+ * 32.  The crop table is passed by value in the kernel arguments, so these
+ * calls allocate nothing and may be captured in a HIP graph.  All volumes
+ * are dense float32 [nz][ny][nx] in device memory; calls are asynchronous on
+ * ex->stream.
+ * ------------------------------------------------------------------ */
+
+typedef struct harpia_crop {
+    const void *in;    /* volume read (forward input, or x for the sigma-gradient) */
+    void *out;         /* volume written */
+    const void *aux;   /* third volume (see each call) */
+    int64_t shape[3];  /* {nz, ny, nx}, each in [1, 2^24] */
+} harpia_crop;
+
+/* Device workspace the batched backward calls need for these crops: FP32
+ * partials of the sigma-gradient and the u16 extremum codes of every crop. */
+size_t harpia_batch_workspace_bytes(const harpia_crop *crops, int32_t n_crops);
+
+/* Gaussian of every crop (in -> out); float32, equal radii 1..12. */
+harpia_status harpia_gaussian3d_batched(const harpia_crop *crops, int32_t n_crops,
+                                        harpia_dtype in_t, harpia_dtype out_t,
+                                        const double sigma[3], double truncate,
+                                        const harpia_exec *ex);
+
+/* Grayscale erosion / dilation of every crop (in -> out); with aux set on
+ * every crop, out receives the erosion and aux the dilation.  float32,
+ * equal radii 1..4. */
+harpia_status harpia_morph3d_batched(const harpia_crop *crops, int32_t n_crops,
+                                     harpia_dtype t, harpia_morph_op op,
+                                     harpia_se se, const int32_t radius[3],
+                                     const harpia_exec *ex);
+
+/* Gaussian gradients over a batch, radii held fixed (equal, 1..12):
+ * per crop in = x, aux = grad_out, out = grad_in (NULL on every crop to
+ * skip).  grad_sigma (device pointer, 3 doubles, or NULL) receives
+ * d/d sigma_{z,y,x} summed over all crops (one sigma shared by the batch):
+ * FP32 workgroup partials in `workspace`, reduced in FP64 in fixed order. */
+harpia_status harpia_gaussian3d_backward_batched(const harpia_crop *crops,
+                                                 int32_t n_crops,
+                                                 const double sigma[3],
+                                                 const int32_t radius[3],
+                                                 double *grad_sigma,
+                                                 void *workspace,
+                                                 size_t workspace_bytes,
+                                                 const harpia_exec *ex);
+
+/* Erosion / dilation subgradient over a batch: per crop in = forward input,
+ * aux = grad_out, out = grad_in; rules of harpia_morph3d_backward.  The
+ * codes live in `workspace` (harpia_batch_workspace_bytes). */
+harpia_status harpia_morph3d_backward_batched(const harpia_crop *crops,
+                                              int32_t n_crops,
+                                              harpia_morph_op op, harpia_se se,
+                                              const int32_t radius[3],
+                                              void *workspace,
+                                              size_t workspace_bytes,
+                                              const harpia_exec *ex);
+
 #ifdef __cplusplus
 }
 #endif

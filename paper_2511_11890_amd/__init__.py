@@ -16,7 +16,8 @@ from ._lib import HarpiaError, harpia_plan, harpia_stats
 
 __all__ = ["gaussian", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
            "plan", "gauss_radius", "version", "HarpiaError", "harpia_stats", "Exec",
-           "gaussian_backward", "morph_backward", "GaussianFn", "MorphFn", "GaussDilateFn"]
+           "gaussian_backward", "morph_backward", "GaussianFn", "MorphFn", "GaussDilateFn",
+           "gaussian_batched", "morph_batched", "GaussDilateBatch"]
 
 
 def _torch():
@@ -305,8 +306,8 @@ def _sigma_grad(sigma, gs):
     if gs is None:
         return None
     if sigma.numel() == 1:
-        return gs.sum().to(sigma.dtype).reshape(sigma.shape)
-    return gs.to(sigma.dtype).reshape(sigma.shape)
+        gs = gs.sum()
+    return gs.to(device=sigma.device, dtype=sigma.dtype).reshape(sigma.shape)
 
 
 def _autograd_base():
@@ -421,6 +422,95 @@ class GaussDilateFn(metaclass=_LazyFunction):
 
             cls._cls = _Fn
         return cls._cls
+
+
+def _stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def gaussian_batched(xs, sigma, truncate: float = 3.0, outs=None):
+    """Gaussian of every crop in one persistent launch per 32 crops (float32
+    device tensors of any shapes; equal radii 1..12)."""
+    torch = _torch()
+    outs = [torch.empty_like(x) for x in xs] if outs is None else outs
+    arr = _lib.crops([(x, o, None) for x, o in zip(xs, outs)])
+    _lib.check(_lib.load().harpia_gaussian3d_batched(arr, len(xs), _lib.HARPIA_F32, _lib.HARPIA_F32,
+                                                     _lib.f64_3(_triple(sigma, float)), float(truncate),
+                                                     _lib.make_exec(stream=_stream())))
+    return outs
+
+
+def morph_batched(xs, op: str, se: str = "box", radius=1, outs=None, outs2=None):
+    """Erosion / dilation of every crop (float32); with outs2 given, outs get
+    the erosion and outs2 the dilation from one launch."""
+    torch = _torch()
+    outs = [torch.empty_like(x) for x in xs] if outs is None else outs
+    aux = outs2 if outs2 is not None else [None] * len(xs)
+    arr = _lib.crops([(x, o, a) for x, o, a in zip(xs, outs, aux)])
+    _lib.check(_lib.load().harpia_morph3d_batched(
+        arr, len(xs), _lib.HARPIA_F32, {"erode": _lib.HARPIA_ERODE, "dilate": _lib.HARPIA_DILATE}[op],
+        {"box": _lib.HARPIA_SE_BOX, "ball": _lib.HARPIA_SE_BALL}[se], _lib.i32_3(_triple(radius, int)),
+        _lib.make_exec(stream=_stream())))
+    return outs
+
+
+class GaussDilateBatch:
+    """Forward and backward of d_i = dilate_se(G_sigma x_i) over a fixed list
+    of float32 crops (the differentiable batched workload), with every buffer
+    allocated up front so that a step allocates nothing and can be captured
+    in a CUDA/HIP graph:
+
+        fwd:  y = G x (batched), d = dilate(y) (batched)
+        bwd:  y = G x recomputed, g_y = routed g_d (argext + gather, batched),
+              g_x = G g_y (batched), d L / d sigma = sum_a <g_y, G'_a x>
+              (batched dot, FP64 reduction) -- kept on the device.
+    sigma is a Python float (isotropic); its radius is resolved once."""
+
+    def __init__(self, xs, sigma: float, se: str = "box", radius=2, truncate: float = 3.0):
+        torch = _torch()
+        self.xs = xs
+        self.sigma = float(sigma)
+        self.r = gauss_radius(self.sigma, truncate)
+        self.se, self.mr = se, radius
+        self.ys = [torch.empty_like(x) for x in xs]
+        self.ds = [torch.empty_like(x) for x in xs]
+        self.gys = [torch.empty_like(x) for x in xs]
+        self.gxs = [torch.empty_like(x) for x in xs]
+        self.gsigma = torch.zeros(3, dtype=torch.float64, device=xs[0].device)
+        self._c_fwd_g = _lib.crops([(x, y, None) for x, y in zip(xs, self.ys)])
+        self._c_fwd_d = _lib.crops([(y, d, None) for y, d in zip(self.ys, self.ds)])
+        nbytes = _lib.load().harpia_batch_workspace_bytes(self._c_fwd_g, len(xs))
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=xs[0].device)
+        self.gds = None
+
+    def forward(self):
+        lib, n, st = _lib.load(), len(self.xs), _lib.make_exec(stream=_stream())
+        s3 = _lib.f64_3((self.sigma,) * 3)
+        _lib.check(lib.harpia_gaussian3d_batched(self._c_fwd_g, n, _lib.HARPIA_F32, _lib.HARPIA_F32, s3, 3.0, st))
+        _lib.check(lib.harpia_morph3d_batched(self._c_fwd_d, n, _lib.HARPIA_F32, _lib.HARPIA_DILATE,
+                                              {"box": 0, "ball": 1}[self.se], _lib.i32_3(_triple(self.mr, int)),
+                                              st))
+        return self.ds
+
+    def backward(self, gds):
+        """gds: upstream gradients (float32 tensors like the crops).  Returns
+        (grad_x list, dL/dsigma_{z,y,x} as a float64 device tensor)."""
+        lib, n, st = _lib.load(), len(self.xs), _lib.make_exec(stream=_stream())
+        if self.gds is not gds:
+            self.gds = gds
+            self._c_bwd_m = _lib.crops([(y, gy, g) for y, gy, g in zip(self.ys, self.gys, gds)])
+            self._c_bwd_g = _lib.crops([(x, gx, gy) for x, gx, gy in zip(self.xs, self.gxs, self.gys)])
+        s3 = _lib.f64_3((self.sigma,) * 3)
+        r3 = _lib.i32_3((self.r,) * 3)
+        ws, wsb = self.workspace.data_ptr(), self.workspace.numel()
+        # recompute y instead of keeping it from the forward
+        _lib.check(lib.harpia_gaussian3d_batched(self._c_fwd_g, n, _lib.HARPIA_F32, _lib.HARPIA_F32, s3, 3.0, st))
+        _lib.check(lib.harpia_morph3d_backward_batched(self._c_bwd_m, n, _lib.HARPIA_DILATE,
+                                                       {"box": 0, "ball": 1}[self.se],
+                                                       _lib.i32_3(_triple(self.mr, int)), ws, wsb, st))
+        _lib.check(lib.harpia_gaussian3d_backward_batched(self._c_bwd_g, n, s3, r3, self.gsigma.data_ptr(), ws,
+                                                          wsb, st))
+        return self.gxs, self.gsigma
 
 
 import ctypes as _ctypes  # noqa: E402

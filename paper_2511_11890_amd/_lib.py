@@ -56,6 +56,11 @@ class harpia_plan(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t)]
 
 
+class harpia_crop(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("aux", ctypes.c_void_p),
+                ("shape", ctypes.c_int64 * 3)]
+
+
 class HarpiaError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
@@ -91,6 +96,16 @@ SIGNATURES = {
                                                   _vp, _ex]),
     "harpia_morph3d_backward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _I64_3, ctypes.c_int,
                                                ctypes.c_int, _I32_3, _ex]),
+    "harpia_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(harpia_crop), ctypes.c_int32]),
+    "harpia_gaussian3d_batched": (ctypes.c_int, [ctypes.POINTER(harpia_crop), ctypes.c_int32, ctypes.c_int,
+                                                 ctypes.c_int, _F64_3, ctypes.c_double, _ex]),
+    "harpia_morph3d_batched": (ctypes.c_int, [ctypes.POINTER(harpia_crop), ctypes.c_int32, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int, _I32_3, _ex]),
+    "harpia_gaussian3d_backward_batched": (ctypes.c_int, [ctypes.POINTER(harpia_crop), ctypes.c_int32, _F64_3,
+                                                          _I32_3, _vp, _vp, ctypes.c_size_t, _ex]),
+    "harpia_morph3d_backward_batched": (ctypes.c_int, [ctypes.POINTER(harpia_crop), ctypes.c_int32,
+                                                       ctypes.c_int, ctypes.c_int, _I32_3, _vp,
+                                                       ctypes.c_size_t, _ex]),
 }
 
 _lib = None
@@ -130,6 +145,18 @@ def i32_3(v):
 
 def f64_3(v):
     return _F64_3(*[float(t) for t in v])
+
+
+def crops(triples):
+    """harpia_crop array from (in, out, aux) tensors (aux / out may be None)."""
+    arr = (harpia_crop * len(triples))()
+    for i, (a, b, c) in enumerate(triples):
+        ref = a if a is not None else (b if b is not None else c)
+        arr[i].in_ = a.data_ptr() if a is not None else None
+        arr[i].out = b.data_ptr() if b is not None else None
+        arr[i].aux = c.data_ptr() if c is not None else None
+        arr[i].shape = i64_3(ref.shape)
+    return arr
 
 
 def make_exec(budget: int = 0, fraction: float = 0.0, chunk=(0, 0, 0), stream: int | None = None,

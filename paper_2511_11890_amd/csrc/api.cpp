@@ -1,9 +1,12 @@
 // C ABI of libharpia (include/harpia.h): argument validation, error
 // reporting and translation of each call into an engine job.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
+#include "batch.h"
 #include "engine.h"
 
 namespace harpia {
@@ -388,10 +391,9 @@ harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t, const 
                 const ChunkArgs a = make_chunk_args(x_reg, g_reg, shape);
                 int64_t nb;
                 if (gauss_fused_ok(dt, a)) {
-                    nb = gauss_dot_blocks(a, dt);
-                    if (!partials.p) partials.alloc((size_t)nb * sizeof(float));
-                    if (launch_gauss_dot(a, x_t, dt, s, static_cast<float *>(partials.p)) != nb)
-                        fail(HARPIA_ERR_UNSUPPORTED, "no fused kernel for these radii");
+                    if (!partials.p) partials.alloc((size_t)gauss_dot_blocks(a, dt) * sizeof(float));
+                    nb = launch_gauss_dot(a, x_t, dt, s, static_cast<float *>(partials.p));
+                    if (nb < 0) fail(HARPIA_ERR_UNSUPPORTED, "no fused kernel for these radii");
                 } else {
                     // unfused: the derivative volume, then its dot with g
                     if (!dvol.p) {
@@ -449,6 +451,201 @@ harpia_status harpia_morph3d_backward(const void *in, harpia_dtype t, const void
             fail(HARPIA_ERR_UNSUPPORTED, "no gather kernel");
         check_hip(hipGetLastError(), "kernel launch");
         check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    });
+}
+
+
+// ------------------------------------------------------------------ batched
+
+static void check_crops(const harpia_crop *crops, int32_t n, bool need_in, bool need_out, bool need_aux)
+{
+    if (!crops || n < 1) fail(HARPIA_ERR_ARG, "crops is NULL or n_crops < 1");
+    for (int32_t i = 0; i < n; ++i) {
+        const harpia_crop &c = crops[i];
+        for (int a = 0; a < 3; ++a)
+            if (c.shape[a] <= 0 || c.shape[a] > (1 << 24)) fail(HARPIA_ERR_ARG, "crop extents must be in [1, 2^24]");
+        if ((double)c.shape[1] * (double)c.shape[2] >= 2147483648.0)
+            fail(HARPIA_ERR_UNSUPPORTED, "crop slices must hold fewer than 2^31 voxels");
+        if ((need_in && !c.in) || (need_out && !c.out) || (need_aux && !c.aux))
+            fail(HARPIA_ERR_ARG, "crop pointer is NULL");
+        if ((c.in && !is_device_pointer(c.in)) || (c.out && !is_device_pointer(c.out)) ||
+            (c.aux && !is_device_pointer(c.aux)))
+            fail(HARPIA_ERR_UNSUPPORTED, "batched calls take device-resident crops");
+    }
+}
+
+// Descriptor of crops [first, first + count) with the given role mapping.
+static BatchDesc make_desc(const harpia_crop *crops, int32_t first, int32_t count, int role)
+{
+    BatchDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.n_crops = count;
+    for (int32_t i = 0; i < count; ++i) {
+        const harpia_crop &c = crops[first + i];
+        BatchCrop &k = d.c[i];
+        switch (role) {
+        case 0: k.in = c.in; k.out = c.out; k.aux = c.aux; break;                 // forward
+        case 1: k.in = c.aux; k.out = c.out; k.aux = nullptr; break;              // grad_in = G grad_out
+        case 2: k.in = c.in; k.out = const_cast<void *>(c.aux); k.aux = nullptr; break;  // dot(G' x, grad_out)
+        }
+        for (int a = 0; a < 3; ++a) k.n[a] = (int32_t)c.shape[a];
+    }
+    return d;
+}
+
+size_t harpia_batch_workspace_bytes(const harpia_crop *crops, int32_t n_crops)
+{
+    // sigma-gradient partials (3 axes x the largest persistent grid per
+    // launch x launches) and u16 argext codes of every crop
+    if (!crops || n_crops < 1) return 0;
+    const int64_t launches = (n_crops + kMaxBatch - 1) / kMaxBatch;
+    size_t bytes = (size_t)(3 * launches * gauss_batched_max_partials()) * sizeof(float);
+    bytes = (bytes + 255) / 256 * 256;
+    for (int32_t i = 0; i < n_crops; ++i) {
+        const size_t v = (size_t)(crops[i].shape[0] * crops[i].shape[1] * crops[i].shape[2]);
+        bytes += (v * sizeof(uint16_t) + 255) / 256 * 256;
+    }
+    return bytes;
+}
+
+harpia_status harpia_gaussian3d_batched(const harpia_crop *crops, int32_t n_crops, harpia_dtype in_t,
+                                        harpia_dtype out_t, const double sigma[3], double truncate,
+                                        const harpia_exec *ex)
+{
+    return guarded([&] {
+        check_exec(ex);
+        if (in_t != HARPIA_F32 || out_t != HARPIA_F32) fail(HARPIA_ERR_DTYPE, "batched calls take float32");
+        if (!sigma) fail(HARPIA_ERR_ARG, "sigma is NULL");
+        check_crops(crops, n_crops, true, true, false);
+        const Stage st = gauss_stage(in_t, out_t, sigma, truncate);
+        if (!(st.r[0] == st.r[1] && st.r[1] == st.r[2]) || st.r[0] < 1 || st.r[0] > kGaussFusedMaxR)
+            fail(HARPIA_ERR_UNSUPPORTED, "batched Gaussian needs equal radii in [1, 12]");
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        for (int32_t f = 0; f < n_crops; f += kMaxBatch) {
+            const int32_t cnt = std::min<int32_t>(kMaxBatch, n_crops - f);
+            if (!launch_gauss_batched(make_desc(crops, f, cnt, 0), in_t, out_t, st.taps, s))
+                fail(HARPIA_ERR_UNSUPPORTED, "no batched Gaussian kernel");
+            check_hip(hipGetLastError(), "kernel launch");
+        }
+    });
+}
+
+harpia_status harpia_morph3d_batched(const harpia_crop *crops, int32_t n_crops, harpia_dtype t,
+                                     harpia_morph_op op, harpia_se se, const int32_t radius[3],
+                                     const harpia_exec *ex)
+{
+    return guarded([&] {
+        check_exec(ex);
+        if (t != HARPIA_F32) fail(HARPIA_ERR_DTYPE, "batched calls take float32");
+        if (op != HARPIA_ERODE && op != HARPIA_DILATE) fail(HARPIA_ERR_ARG, "unknown morphology op");
+        const MorphArgs m = check_morph(t, se, radius, std::nan(""), HARPIA_BORDER_REFLECT, nullptr);
+        if (!(m.r[0] == m.r[1] && m.r[1] == m.r[2]) || m.r[0] < 1 || m.r[0] > 4)
+            fail(HARPIA_ERR_UNSUPPORTED, "batched morphology needs equal radii in [1, 4]");
+        check_crops(crops, n_crops, true, true, false);
+        const bool both = crops[0].aux != nullptr;
+        for (int32_t i = 0; i < n_crops; ++i)
+            if ((crops[i].aux != nullptr) != both) fail(HARPIA_ERR_ARG, "aux must be set for all crops or none");
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        for (int32_t f = 0; f < n_crops; f += kMaxBatch) {
+            const int32_t cnt = std::min<int32_t>(kMaxBatch, n_crops - f);
+            if (!launch_morph_batched(make_desc(crops, f, cnt, 0), t, (int)op, (int)se, m.r[0], both, s))
+                fail(HARPIA_ERR_UNSUPPORTED, "no batched morphology kernel");
+            check_hip(hipGetLastError(), "kernel launch");
+        }
+    });
+}
+
+harpia_status harpia_gaussian3d_backward_batched(const harpia_crop *crops, int32_t n_crops,
+                                                 const double sigma[3], const int32_t radius[3],
+                                                 double *grad_sigma, void *workspace, size_t workspace_bytes,
+                                                 const harpia_exec *ex)
+{
+    return guarded([&] {
+        check_exec(ex);
+        if (!sigma || !radius) fail(HARPIA_ERR_ARG, "sigma / radius is NULL");
+        for (int a = 0; a < 3; ++a)
+            if (!(sigma[a] > 0.0) || !std::isfinite(sigma[a])) fail(HARPIA_ERR_ARG, "sigma must be finite and > 0");
+        if (!(radius[0] == radius[1] && radius[1] == radius[2]) || radius[0] < 1 || radius[0] > kGaussFusedMaxR)
+            fail(HARPIA_ERR_UNSUPPORTED, "batched Gaussian needs equal radii in [1, 12]");
+        check_crops(crops, n_crops, grad_sigma != nullptr, false, true);
+        const bool want_in = crops[0].out != nullptr;
+        for (int32_t i = 0; i < n_crops; ++i)
+            if ((crops[i].out != nullptr) != want_in) fail(HARPIA_ERR_ARG, "out must be set for all crops or none");
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        const int r[3] = {radius[0], radius[1], radius[2]};
+        if (want_in) {
+            GaussTaps taps;
+            make_gauss_taps_r(sigma, r, taps);
+            for (int32_t f = 0; f < n_crops; f += kMaxBatch) {
+                const int32_t cnt = std::min<int32_t>(kMaxBatch, n_crops - f);
+                if (!launch_gauss_batched(make_desc(crops, f, cnt, 1), HARPIA_F32, HARPIA_F32, taps, s))
+                    fail(HARPIA_ERR_UNSUPPORTED, "no batched Gaussian kernel");
+                check_hip(hipGetLastError(), "kernel launch");
+            }
+        }
+        if (grad_sigma) {
+            if (!is_device_pointer(grad_sigma)) fail(HARPIA_ERR_ARG, "grad_sigma must be a device pointer");
+            const int64_t launches = (n_crops + kMaxBatch - 1) / kMaxBatch;
+            const size_t need = (size_t)(3 * launches * gauss_batched_max_partials()) * sizeof(float);
+            if (!workspace || workspace_bytes < need) fail(HARPIA_ERR_ARG, "workspace too small");
+            if (!is_device_pointer(workspace)) fail(HARPIA_ERR_ARG, "workspace must be device memory");
+            float *part = static_cast<float *>(workspace);
+            for (int axis = 0; axis < 3; ++axis) {
+                GaussTaps dt;
+                make_gauss_dtaps_r(sigma, r, axis, dt);
+                int64_t n = 0;
+                for (int32_t f = 0; f < n_crops; f += kMaxBatch) {
+                    const int32_t cnt = std::min<int32_t>(kMaxBatch, n_crops - f);
+                    const int64_t got =
+                        launch_gauss_dot_batched(make_desc(crops, f, cnt, 2), HARPIA_F32, dt, s, part + n);
+                    if (got < 0) fail(HARPIA_ERR_UNSUPPORTED, "no batched dot kernel");
+                    check_hip(hipGetLastError(), "kernel launch");
+                    n += got;
+                }
+                launch_reduce_f64(part, n, grad_sigma + axis, false, s);
+                check_hip(hipGetLastError(), "kernel launch");
+                part += launches * gauss_batched_max_partials();
+            }
+        }
+    });
+}
+
+harpia_status harpia_morph3d_backward_batched(const harpia_crop *crops, int32_t n_crops, harpia_morph_op op,
+                                              harpia_se se, const int32_t radius[3], void *workspace,
+                                              size_t workspace_bytes, const harpia_exec *ex)
+{
+    return guarded([&] {
+        check_exec(ex);
+        if (op != HARPIA_ERODE && op != HARPIA_DILATE) fail(HARPIA_ERR_ARG, "unknown morphology op");
+        const MorphArgs m = check_morph(HARPIA_F32, se, radius, std::nan(""), HARPIA_BORDER_REFLECT, nullptr);
+        if (!morph_grad_supported(m.r)) fail(HARPIA_ERR_UNSUPPORTED, "morphology gradient radius above 8");
+        check_crops(crops, n_crops, true, true, true);
+        const size_t need = harpia_batch_workspace_bytes(crops, n_crops);
+        if (!workspace || workspace_bytes < need) fail(HARPIA_ERR_ARG, "workspace too small");
+        if (!is_device_pointer(workspace)) fail(HARPIA_ERR_ARG, "workspace must be device memory");
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        // codes live after the sigma-gradient partials
+        const int64_t launches = (n_crops + kMaxBatch - 1) / kMaxBatch;
+        size_t off = ((size_t)(3 * launches * gauss_batched_max_partials()) * sizeof(float) + 255) / 256 * 256;
+        std::vector<void *> codes(n_crops);
+        for (int32_t i = 0; i < n_crops; ++i) {
+            codes[i] = static_cast<char *>(workspace) + off;
+            const size_t v = (size_t)(crops[i].shape[0] * crops[i].shape[1] * crops[i].shape[2]);
+            off += (v * sizeof(uint16_t) + 255) / 256 * 256;
+        }
+        for (int32_t f = 0; f < n_crops; f += kMaxBatch) {
+            const int32_t cnt = std::min<int32_t>(kMaxBatch, n_crops - f);
+            BatchDesc d = make_desc(crops, f, cnt, 0);
+            // argext: in = forward input, aux = codes
+            for (int32_t i = 0; i < cnt; ++i) d.c[i].aux = codes[f + i];
+            if (!launch_argext_batched(d, HARPIA_F32, (int)op, (int)se, m.r, s))
+                fail(HARPIA_ERR_UNSUPPORTED, "no batched argext kernel");
+            check_hip(hipGetLastError(), "kernel launch");
+            // gather: in = upstream gradient, aux = codes, out = grad_in
+            for (int32_t i = 0; i < cnt; ++i) d.c[i].in = crops[f + i].aux;
+            if (!launch_gather_batched(d, (int)se, m.r, s)) fail(HARPIA_ERR_UNSUPPORTED, "no batched gather kernel");
+            check_hip(hipGetLastError(), "kernel launch");
+        }
     });
 }
 

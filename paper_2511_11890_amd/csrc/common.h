@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <string>
 
 #include "harpia.h"
@@ -69,6 +70,17 @@ template <> __device__ __forceinline__ uint16_t from_f32<uint16_t>(float v)
 template <> __device__ __forceinline__ uint8_t from_f32<uint8_t>(float v)
 {
     return (uint8_t)v;
+}
+
+// Workgroup barrier that orders LDS only.  __syncthreads() also fences
+// global memory, which makes every wave wait for all of its outstanding
+// global loads (vmcnt(0)) at each barrier and so defeats prefetching the
+// next slices; the streaming kernels exchange data through LDS only.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // ------------------------------------------------------------ reflection
@@ -140,6 +152,51 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb)
 
 // ------------------------------------------------------------ launchers
 
+// Workgroups of `kernel` the whole device holds at once (occupancy per CU x
+// CU count); at least 1.
+template <class K>
+inline int64_t resident_blocks(K kernel, int threads, size_t dyn_lds = 0)
+{
+    int dev = 0, cus = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, dyn_lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1024;
+    }
+    return (int64_t)(nb > 0 ? nb : 1) * (cus > 0 ? cus : 1);
+}
+
+// Number of z ranges to split `nz` output slices into, for `tiles` xy tiles
+// per range on a device holding `capacity` workgroups at once: minimises
+// (rounds of resident workgroups) x (slices one workgroup streams, its 2r
+// warm-up included), preferring fewer ranges on ties.
+inline int64_t z_ranges(int64_t nz, int64_t tiles, int64_t capacity, int r, int64_t max_ranges = 64)
+{
+    // HARPIA_ZRANGES=n forces n ranges (a tuning knob: the same work, split
+    // differently across workgroups)
+    static const int64_t forced = [] {
+        const char *e = std::getenv("HARPIA_ZRANGES");
+        return (e && *e) ? (int64_t)std::atoll(e) : (int64_t)0;
+    }();
+    if (forced > 0) {
+        const int64_t n = forced < nz ? forced : nz;
+        return n < max_ranges ? n : max_ranges;
+    }
+    int64_t best_n = 1;
+    double best = 1e300;
+    for (int64_t zc = 1; zc <= nz && zc <= max_ranges; ++zc) {
+        const int64_t zlen = (nz + zc - 1) / zc;
+        const int64_t n = (nz + zlen - 1) / zlen;
+        const int64_t rounds = (tiles * n + capacity - 1) / capacity;
+        const double cost = (double)rounds * (double)(zlen + 2 * r);
+        if (cost < best * 0.999) {
+            best = cost;
+            best_n = n;
+        }
+    }
+    return best_n;
+}
 constexpr int kMaxGaussRadius = 64;  // unfused-path limit per axis
 constexpr int kGaussFusedMaxR = 12;  // fused z-streaming kernel: 1 <= r <= this
 
@@ -187,6 +244,7 @@ float compare_threshold(harpia_dtype t, double thr);
 // taps / dtype need the unfused path.
 int64_t launch_gauss_dot(const ChunkArgs &a, harpia_dtype in_t, const GaussTaps &taps, hipStream_t s,
                          float *partials);
+// Upper bound of the partials launch_gauss_dot writes.
 int64_t gauss_dot_blocks(const ChunkArgs &a, const GaussTaps &taps);
 bool gauss_fused_ok(const GaussTaps &taps, const ChunkArgs &a);
 // sum of partials[0..n) in FP64, fixed order, into out[0] (or added to it).

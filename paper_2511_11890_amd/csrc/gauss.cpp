@@ -27,6 +27,7 @@
 
 #include "common.h"
 #include "gauss_grid.h"
+#include "batch.h"
 
 namespace harpia {
 
@@ -34,6 +35,27 @@ template <typename Tin, typename Tout>
 bool gauss_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes);
 template <typename Tin>
 int64_t gauss_dot_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials);
+template <typename Tin, typename Tout>
+bool gauss_batched_run(const BatchDesc &d, const GaussTaps &taps, hipStream_t s);
+template <typename Tin>
+int64_t gauss_dot_batched_run(const BatchDesc &d, const GaussTaps &taps, hipStream_t s, float *partials);
+
+// Batched kernels are built for float32 volumes (the differentiable path).
+bool launch_gauss_batched(const BatchDesc &d, harpia_dtype in_t, harpia_dtype out_t, const GaussTaps &taps,
+                          hipStream_t s)
+{
+    if (in_t != HARPIA_F32 || out_t != HARPIA_F32) return false;
+    return gauss_batched_run<float, float>(d, taps, s);
+}
+
+int64_t launch_gauss_dot_batched(const BatchDesc &d, harpia_dtype in_t, const GaussTaps &taps, hipStream_t s,
+                                 float *partials)
+{
+    if (in_t != HARPIA_F32) return -1;
+    return gauss_dot_batched_run<float>(d, taps, s, partials);
+}
+
+int64_t gauss_batched_max_partials() { return 8192; }
 
 size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3])
 {
@@ -85,7 +107,8 @@ bool gauss_fused_ok(const GaussTaps &taps, const ChunkArgs &a) { return gauss_de
 
 int64_t gauss_dot_blocks(const ChunkArgs &a, const GaussTaps &taps)
 {
-    return gauss_detail::fused_grid(a, taps.r[0]).blocks;
+    (void)taps;
+    return gauss_detail::fused_blocks_bound(a);
 }
 
 int64_t launch_gauss_dot(const ChunkArgs &a, harpia_dtype in_t, const GaussTaps &taps, hipStream_t s,

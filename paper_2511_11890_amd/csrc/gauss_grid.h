@@ -15,29 +15,27 @@ struct FusedGrid {
     int64_t blocks;
 };
 
-inline FusedGrid fused_grid(const ChunkArgs &a, int R)
+// Largest number of z ranges a launch uses (bounds the sigma-gradient
+// partials: one per workgroup).
+constexpr int64_t kMaxZRanges = 64;
+
+inline FusedGrid fused_grid(const ChunkArgs &a, int R, int64_t capacity)
 {
     FusedGrid g;
     g.tiles_x = (int)((a.out_e[2] + kTX - 1) / kTX);
     g.tiles_y = (int)((a.out_e[1] + kTY - 1) / kTY);
     const int64_t tiles = (int64_t)g.tiles_x * g.tiles_y;
-    // z range per workgroup: enough workgroups to fill the chip several
-    // times over, but long enough that the 2r-slice warm-up stays small.
-    int64_t zlen = a.out_e[0];
-    const int64_t want_blocks = 4096;
-    if (tiles < want_blocks) {
-        int64_t nzc = (want_blocks + tiles - 1) / tiles;
-        zlen = (a.out_e[0] + nzc - 1) / nzc;
-        const int64_t min_len = 8 * R > 32 ? 8 * R : 32;
-        if (zlen < min_len) zlen = min_len;
-    } else {
-        const int64_t max_len = 256;
-        if (zlen > max_len && tiles < 4 * want_blocks) zlen = max_len;
-    }
-    if (zlen > a.out_e[0]) zlen = a.out_e[0];
-    g.zlen = (int)zlen;
-    g.blocks = tiles * ((a.out_e[0] + zlen - 1) / zlen);
+    const int64_t nzc = z_ranges(a.out_e[0], tiles, capacity, R, kMaxZRanges);
+    g.zlen = (int)((a.out_e[0] + nzc - 1) / nzc);
+    g.blocks = tiles * ((a.out_e[0] + g.zlen - 1) / g.zlen);
     return g;
+}
+
+// Upper bound of fused_grid(...).blocks over every capacity.
+inline int64_t fused_blocks_bound(const ChunkArgs &a)
+{
+    const int64_t tiles = ((a.out_e[2] + kTX - 1) / kTX) * ((a.out_e[1] + kTY - 1) / kTY);
+    return tiles * (a.out_e[0] < kMaxZRanges ? a.out_e[0] : kMaxZRanges);
 }
 
 inline bool fused_ok(const GaussTaps &t, const ChunkArgs &a)

@@ -31,6 +31,7 @@
 
 #include "common.h"
 #include "gauss_grid.h"
+#include "batch.h"
 
 namespace harpia {
 
@@ -56,40 +57,42 @@ constexpr int kMY = 4;    // rows per y-pass work item
 
 static_assert(kTX / 4 * kTY == kNT, "x pass maps one 4-column quad per thread");
 
+// Store 4 consecutive outputs: one 16-byte (f32) or 8-byte (16-bit) store
+// when all 4 are inside the region and the address is aligned, else element
+// by element.
 template <typename T>
 __device__ __forceinline__ void store4(T *p, const float v[4], int nvalid)
 {
-    if (nvalid >= 4) {
+    constexpr uintptr_t kAlignMask = sizeof(T) * 4 - 1;
+    if (nvalid == 4 && (reinterpret_cast<uintptr_t>(p) & kAlignMask) == 0) {
         if constexpr (sizeof(T) == 4) {
-            if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
-                float4 q = make_float4(v[0], v[1], v[2], v[3]);
-                *reinterpret_cast<float4 *>(p) = q;
-                return;
-            }
-        } else if constexpr (sizeof(T) == 2) {
-            if ((reinterpret_cast<uintptr_t>(p) & 7) == 0) {
-                uint16_t h[4];
+            float4 q = make_float4(v[0], v[1], v[2], v[3]);
+            *reinterpret_cast<float4 *>(p) = q;
+        } else {
+            uint16_t hb[4];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    T t = from_f32<T>(v[c]);
-                    h[c] = *reinterpret_cast<uint16_t *>(&t);
-                }
-                uint2 q = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
-                                     (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-                *reinterpret_cast<uint2 *>(p) = q;
-                return;
+            for (int c = 0; c < 4; ++c) {
+                T t = from_f32<T>(v[c]);
+                hb[c] = *reinterpret_cast<uint16_t *>(&t);
             }
+            *reinterpret_cast<uint2 *>(p) = make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16),
+                                                       (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
         }
-    }
+    } else {
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-        if (c < nvalid) p[c] = from_f32<T>(v[c]);
+        for (int c = 0; c < 4; ++c)
+            if (c < nvalid) p[c] = from_f32<T>(v[c]);
+    }
 }
 
-// Slices of input kept in flight per thread (the prefetch ring depth): deep
-// enough that the loads issued for slice i + D cover the HBM latency while
-// slices i .. i + D - 1 are filtered, shallow enough to keep occupancy.
-constexpr int gauss_prefetch_depth(int R) { return R <= 4 ? 3 : (R <= 8 ? 2 : 1); }
+constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
+constexpr int lcm_int(int a, int b) { return a / gcd_int(a, b) * b; }
+
+// Slices of input in flight per thread beyond the one being filtered.  With
+// the LDS-only barrier one slice already overlaps a whole step; deeper rings
+// make the compiler wait for them early (its wait counts merge
+// conservatively across the step's branches).
+constexpr int gauss_prefetch_depth(int) { return 1; }
 
 // Output policies of the fused tile.  put(off, nvalid, v) receives the 4
 // finished outputs of one thread at element offset `off` of the output
@@ -182,28 +185,25 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
     const int64_t s0 = zo0 - R;
     const int nsteps = (int)(zo1 - zo0) + 2 * R;  // input slices of this range
 
-    // Prefetch ring: at the start of step i, pf[k] holds slice i + 1 + k.
-    // It keeps the raw loaded values; converting them at load time would make
-    // the loads complete before the next slice is filtered.
+    // Prefetch ring of D slices: slot j mod D holds slice j.  Slot indices
+    // are compile-time constants (the step loop is unrolled lcm(P, D)
+    // times) and every fetch is unconditional (past the last slice it
+    // re-reads the last one, which is never used), so the ring needs no
+    // register moves and its loads stay in flight until they are staged.
     Tin pf[D][NLD];
     auto fetch = [&](int j, Tin(&dst)[NLD]) __attribute__((always_inline)) {
+        j = j < nsteps ? j : nsteps - 1;
         const int64_t zl = reflect_index(s0 + j, a.n[0]) - a.in_o[0];
         const Tin *base = in + zl * a.in_sz;
 #pragma unroll
         for (int k = 0; k < NLD; ++k)
             if (k < NLD - 1 || tid + k * kNT < PSZ) dst[k] = base[off[k]];
     };
-    auto stage_and_advance = [&](int j) __attribute__((always_inline)) {
-        // pf[0] holds slice j: store it, shift the ring, fetch slice j + D
+    auto stage = [&](int j, const Tin(&src)[NLD]) __attribute__((always_inline)) {
         float *dst = sP + (j & 1) * PSZ;
 #pragma unroll
         for (int k = 0; k < NLD; ++k)
-            if (k < NLD - 1 || tid + k * kNT < PSZ) dst[tid + k * kNT] = to_f32(pf[0][k]);
-#pragma unroll
-        for (int d = 0; d + 1 < D; ++d)
-#pragma unroll
-            for (int k = 0; k < NLD; ++k) pf[d][k] = pf[d + 1][k];
-        if (j + D < nsteps) fetch(j + D, pf[D - 1]);
+            if (k < NLD - 1 || tid + k * kNT < PSZ) dst[tid + k * kNT] = to_f32(src[k]);
     };
 
     const int qrow = tid / (kTX / 4);
@@ -219,18 +219,18 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[j][c] = 0.f;
 
-#pragma unroll
-    for (int d = 0; d < D; ++d)
-        if (d < nsteps) fetch(d, pf[d]);
-    stage_and_advance(0);
-    __syncthreads();
+    static_for<D>([&](auto DD) { fetch(decltype(DD)::value, pf[decltype(DD)::value]); });
+    stage(0, pf[0]);
+    fetch(D, pf[0]);
+    lds_barrier();
 
     // Step i: x and z passes of slice i - 1, y pass of slice i, staging of
     // slice i + 1.  Steps run 0 .. nsteps; the slot of output o in the z
     // ring is (o - s0) mod P, and slice j feeds outputs j - R .. j + R.
-    for (int base = 0; base <= nsteps; base += P) {
-        static_for<P>([&](auto U) {
-            constexpr int u = decltype(U)::value;
+    constexpr int U = lcm_int(P, D);
+    for (int base = 0; base <= nsteps; base += U) {
+        static_for<U>([&](auto UU) {
+            constexpr int u = decltype(UU)::value;
             const int i = base + u;
             if (i > nsteps) return;
 
@@ -263,17 +263,15 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
 #pragma unroll
                     for (int c = 0; c < 4; ++c) acc[sl][c] = (d == R) ? wd * t[c] : fmaf(wd, t[c], acc[sl][c]);
                 });
-                if (i - 1 >= 2 * R) {
-                    constexpr int sl = (u - 1 - R + 2 * P) % P;
-                    const int64_t o = s0 + (i - 1) - R;
-                    out.put(col_off + (o - a.out_o[0]) * a.out_sz, nvalid, acc[sl]);
-                }
             }
             if (i < nsteps) {
                 // y pass of slice i: sP (PH x PW) -> sQ (kTY x PW)
                 const float *p = sP + (i & 1) * PSZ;
                 float *q = sQ + (i & 1) * QSZ;
-                for (int it = tid; it < NYI; it += kNT) {
+#pragma unroll
+                for (int itk = 0; itk < (NYI + kNT - 1) / kNT; ++itk) {
+                    const int it = tid + itk * kNT;
+                    if (itk == (NYI + kNT - 1) / kNT - 1 && it >= NYI) continue;
                     const int col = it % PW, rg = it / PW;
                     float v[kMY + 2 * R];
 #pragma unroll
@@ -286,9 +284,21 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
                         q[(rg * kMY + m) * QP + col] = sacc;
                     }
                 }
-                if (i + 1 < nsteps) stage_and_advance(i + 1);
-                __syncthreads();
+                // stage slice i + 1 and refill its slot with slice i + 1 + D
+                constexpr int slot = (u + 1) % D;
+                stage(i + 1, pf[slot]);
+                fetch(i + 1 + D, pf[slot]);
             }
+            // Output i - 1 - R is complete.  Stored after the fetch so that
+            // staging the next slice does not wait for these stores (global
+            // loads and stores share one in-order completion counter).  Its
+            // ring slot is first rewritten by the next step.
+            if (i >= 1 && i - 1 >= 2 * R) {
+                constexpr int sl = (u - 1 - R + 2 * P) % P;
+                const int64_t o = s0 + (i - 1) - R;
+                out.put(col_off + (o - a.out_o[0]) * a.out_sz, nvalid, acc[sl]);
+            }
+            if (i < nsteps) lds_barrier();
         });
     }
 }
@@ -317,9 +327,9 @@ __device__ __forceinline__ float block_sum_256(float v)
     __shared__ float wsum[kNT / 64];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    __syncthreads();
+    lds_barrier();
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
-    __syncthreads();
+    lds_barrier();
     return (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
 }
 
@@ -336,6 +346,42 @@ __global__ __launch_bounds__(kNT) void gauss_dot_kernel(ChunkArgs a, GaussTaps t
     gauss_tile<Tin, R, D>(a, taps, zlen, bx, by, bz, out);
     const float t = block_sum_256(out.sum);
     if (threadIdx.x == 0) partials[b] = t;
+}
+
+// Persistent batched Gaussian: workgroup b takes work items
+// xcd_remap(b) + k * gridDim (so the workgroups of one XCD hold neighbouring
+// tiles at any time); the LDS of the tile routine is reused between items.
+template <typename Tin, typename Tout, int R, int D = gauss_prefetch_depth(R)>
+__global__ __launch_bounds__(kNT) void gauss_batched_kernel(BatchDesc d, GaussTaps taps)
+{
+    const int total = d.prefix[d.n_crops];
+    for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
+        int c, bx, by, bz;
+        batch_item(d, w, c, bx, by, bz);
+        const ChunkArgs a = crop_args(d.c[c]);
+        StoreOut<Tout> out{static_cast<Tout *>(a.out)};
+        gauss_tile<Tin, R, D>(a, taps, d.c[c].zlen, bx, by, bz, out);
+        lds_barrier();
+    }
+}
+
+// Batched sigma-gradient term: one FP32 partial per workgroup over all of
+// its items (in = x, out = upstream gradient).
+template <typename Tin, int R, int D = gauss_prefetch_depth(R)>
+__global__ __launch_bounds__(kNT) void gauss_dot_batched_kernel(BatchDesc d, GaussTaps taps, float *partials)
+{
+    const int total = d.prefix[d.n_crops];
+    DotOut out{nullptr, 0.f};
+    for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
+        int c, bx, by, bz;
+        batch_item(d, w, c, bx, by, bz);
+        const ChunkArgs a = crop_args(d.c[c]);
+        out.g = static_cast<const float *>(a.out);
+        gauss_tile<Tin, R, D>(a, taps, d.c[c].zlen, bx, by, bz, out);
+        lds_barrier();
+    }
+    const float t = block_sum_256(out.sum);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
 // One 1D pass along `axis` (0 z, 1 y, 2 x): dst = w * src, reflect along the
@@ -368,27 +414,29 @@ __global__ __launch_bounds__(256) void gauss_pass_kernel(const Tin *src, int64_t
 template <typename Tin, typename Tout, int R>
 void launch_fused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
-    const FusedGrid g = fused_grid(a, R);
+    static const int64_t cap = resident_blocks(gauss_fused_kernel<Tin, Tout, R>, kNT);
+    const FusedGrid g = fused_grid(a, R, cap);
     hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, taps,
                        g.zlen, g.tiles_x, g.tiles_y);
 }
 
 template <typename Tin, int R>
-void launch_dot(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
+int64_t launch_dot(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
 {
-    const FusedGrid g = fused_grid(a, R);
+    static const int64_t cap = resident_blocks(gauss_dot_kernel<Tin, R>, kNT);
+    const FusedGrid g = fused_grid(a, R, cap);
     hipLaunchKernelGGL((gauss_dot_kernel<Tin, R>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, taps, g.zlen,
                        g.tiles_x, g.tiles_y, partials);
+    return g.blocks;
 }
 
 template <typename Tin>
-bool dispatch_dot(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
+int64_t dispatch_dot(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
 {
     switch (r) {
-#define HARPIA_CASE(RR)                           \
-    case RR:                                      \
-        launch_dot<Tin, RR>(a, taps, s, partials); \
-        return true;
+#define HARPIA_CASE(RR) \
+    case RR:            \
+        return launch_dot<Tin, RR>(a, taps, s, partials);
         HARPIA_CASE(1)
         HARPIA_CASE(2)
         HARPIA_CASE(3)
@@ -429,7 +477,7 @@ bool dispatch_fused(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_
         HARPIA_CASE(12)
 #undef HARPIA_CASE
     default:
-        return false;
+        return -1;
     }
 }
 
@@ -483,7 +531,99 @@ bool run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch
     return true;
 }
 
+// z range per batched work item: short enough that a batch of crops yields
+// many items per resident workgroup, long enough to amortise the 2r warm-up.
+constexpr int kBatchZ = 32;
+constexpr int64_t kBatchMaxGrid = 8192;
+
+template <typename Tin, typename Tout, int R>
+void launch_batched(BatchDesc d, const GaussTaps &taps, hipStream_t s)
+{
+    static const int64_t cap = resident_blocks(gauss_batched_kernel<Tin, Tout, R>, kNT);
+    batch_layout(d, kTX, kTY, kBatchZ);
+    const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < kBatchMaxGrid ? cap : kBatchMaxGrid);
+    if (grid > 0)
+        hipLaunchKernelGGL((gauss_batched_kernel<Tin, Tout, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, taps);
+}
+
+template <typename Tin, int R>
+int64_t launch_dot_batched(BatchDesc d, const GaussTaps &taps, hipStream_t s, float *partials)
+{
+    static const int64_t cap = resident_blocks(gauss_dot_batched_kernel<Tin, R>, kNT);
+    batch_layout(d, kTX, kTY, kBatchZ);
+    const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < kBatchMaxGrid ? cap : kBatchMaxGrid);
+    if (grid > 0)
+        hipLaunchKernelGGL((gauss_dot_batched_kernel<Tin, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, taps,
+                           partials);
+    return grid;
+}
+
+template <typename Tin, typename Tout>
+bool dispatch_batched(int r, const BatchDesc &d, const GaussTaps &taps, hipStream_t s)
+{
+    switch (r) {
+#define HARPIA_CASE(RR)                               \
+    case RR:                                          \
+        launch_batched<Tin, Tout, RR>(d, taps, s);    \
+        return true;
+        HARPIA_CASE(1)
+        HARPIA_CASE(2)
+        HARPIA_CASE(3)
+        HARPIA_CASE(4)
+        HARPIA_CASE(5)
+        HARPIA_CASE(6)
+        HARPIA_CASE(7)
+        HARPIA_CASE(8)
+        HARPIA_CASE(9)
+        HARPIA_CASE(10)
+        HARPIA_CASE(11)
+        HARPIA_CASE(12)
+#undef HARPIA_CASE
+    default:
+        return false;
+    }
+}
+
+template <typename Tin>
+int64_t dispatch_dot_batched(int r, const BatchDesc &d, const GaussTaps &taps, hipStream_t s, float *partials)
+{
+    switch (r) {
+#define HARPIA_CASE(RR) \
+    case RR:            \
+        return launch_dot_batched<Tin, RR>(d, taps, s, partials);
+        HARPIA_CASE(1)
+        HARPIA_CASE(2)
+        HARPIA_CASE(3)
+        HARPIA_CASE(4)
+        HARPIA_CASE(5)
+        HARPIA_CASE(6)
+        HARPIA_CASE(7)
+        HARPIA_CASE(8)
+        HARPIA_CASE(9)
+        HARPIA_CASE(10)
+        HARPIA_CASE(11)
+        HARPIA_CASE(12)
+#undef HARPIA_CASE
+    default:
+        return -1;
+    }
+}
+
 }  // namespace gauss_detail
+
+template <typename Tin, typename Tout>
+bool gauss_batched_run(const BatchDesc &d, const GaussTaps &taps, hipStream_t s)
+{
+    if (!(taps.r[0] == taps.r[1] && taps.r[1] == taps.r[2])) return false;
+    return gauss_detail::dispatch_batched<Tin, Tout>(taps.r[0], d, taps, s);
+}
+
+template <typename Tin>
+int64_t gauss_dot_batched_run(const BatchDesc &d, const GaussTaps &taps, hipStream_t s, float *partials)
+{
+    if (!(taps.r[0] == taps.r[1] && taps.r[1] == taps.r[2])) return -1;
+    return gauss_detail::dispatch_dot_batched<Tin>(taps.r[0], d, taps, s, partials);
+}
 
 template <typename Tin, typename Tout>
 bool gauss_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes)
@@ -497,8 +637,7 @@ template <typename Tin>
 int64_t gauss_dot_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
 {
     if (!gauss_detail::fused_ok(taps, a)) return -1;
-    if (!gauss_detail::dispatch_dot<Tin>(taps.r[0], a, taps, s, partials)) return -1;
-    return gauss_detail::fused_grid(a, taps.r[0]).blocks;
+    return gauss_detail::dispatch_dot<Tin>(taps.r[0], a, taps, s, partials);
 }
 
 }  // namespace harpia

@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "batch.h"
 
 namespace harpia {
 
@@ -35,10 +36,10 @@ __global__ __launch_bounds__(256) void reduce_partials_f64(const float *partials
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)partials[i];
     sh[threadIdx.x] = s;
-    __syncthreads();
+    lds_barrier();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
+        lds_barrier();
     }
     if (threadIdx.x == 0) out[0] = accumulate ? out[0] + sh[0] : sh[0];
 }
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(256) void dot_partials_kernel(const float *a, int64
     __shared__ float wsum[4];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) partials[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
 }
 
@@ -66,13 +67,17 @@ struct TileGeom {
     int hz, hy, hx;      // LDS tile extent (tile + 2r)
 };
 
-__device__ __forceinline__ TileGeom tile_geom(const ChunkArgs &a, int rz, int ry, int rx, int tiles_x, int tiles_y)
+__device__ __forceinline__ void block_tile(int tiles_x, int tiles_y, int &bx, int &by, int &bz)
+{
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    bx = (int)(b % (uint32_t)tiles_x);
+    by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
+    bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
+}
+
+__device__ __forceinline__ TileGeom tile_geom(const ChunkArgs &a, int rz, int ry, int rx, int bx, int by, int bz)
 {
     TileGeom t;
-    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int bx = (int)(b % (uint32_t)tiles_x);
-    const int by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
-    const int bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
     t.x0 = a.out_o[2] + (int64_t)bx * kGX;
     t.y0 = a.out_o[1] + (int64_t)by * kGY;
     t.z0 = a.out_o[0] + (int64_t)bz * kGZ;
@@ -89,11 +94,10 @@ __device__ __forceinline__ bool in_element(int se, int r, int dz, int dy, int dx
 
 // code[p] for every p of the output region (codes laid out like a.out, u16).
 template <typename T>
-__global__ __launch_bounds__(kGT) void argext_kernel(ChunkArgs a, uint16_t *code, int op, int se, int rz, int ry,
-                                                     int rx, int tiles_x, int tiles_y)
+__device__ __forceinline__ void argext_tile(const ChunkArgs &a, uint16_t *code, int op, int se, int rz, int ry,
+                                            int rx, int bx, int by, int bz, float *sv)
 {
-    extern __shared__ float sv[];
-    const TileGeom t = tile_geom(a, rz, ry, rx, tiles_x, tiles_y);
+    const TileGeom t = tile_geom(a, rz, ry, rx, bx, by, bz);
     const int n_lds = t.hz * t.hy * t.hx;
     const T *in = static_cast<const T *>(a.in);
     // stage the tile; positions outside the volume are clamped (never read:
@@ -110,14 +114,14 @@ __global__ __launch_bounds__(kGT) void argext_kernel(ChunkArgs a, uint16_t *code
         gx = gx < a.in_o[2] ? a.in_o[2] : gx;
         sv[e] = to_f32(in[(gz - a.in_o[0]) * a.in_sz + (gy - a.in_o[1]) * a.in_sy + (gx - a.in_o[2])]);
     }
-    __syncthreads();
+    lds_barrier();
     const int tx = threadIdx.x % kGX, ty = threadIdx.x / kGX;
     const int64_t gx = t.x0 + tx, gy = t.y0 + ty;
     const int64_t xend = a.out_o[2] + a.out_e[2], yend = a.out_o[1] + a.out_e[1];
     const int64_t zend = a.out_o[0] + a.out_e[0];
-    if (gx >= xend || gy >= yend) return;
+    const bool active = gx < xend && gy < yend;
     const int wx = 2 * rx + 1, wyx = (2 * ry + 1) * wx;
-    for (int tz = 0; tz < kGZ; ++tz) {
+    for (int tz = 0; active && tz < kGZ; ++tz) {
         const int64_t gz = t.z0 + tz;
         if (gz >= zend) break;
         float best = 0.f;
@@ -144,13 +148,38 @@ __global__ __launch_bounds__(kGT) void argext_kernel(ChunkArgs a, uint16_t *code
     }
 }
 
-// gin over the output region of `a` (gin laid out like a.out); g and code
-// laid out like the input region of `a` (a.in describes them: in = g).
-__global__ __launch_bounds__(kGT) void gather_kernel(ChunkArgs a, const uint16_t *code, int se, int rz, int ry,
+template <typename T>
+__global__ __launch_bounds__(kGT) void argext_kernel(ChunkArgs a, uint16_t *code, int op, int se, int rz, int ry,
                                                      int rx, int tiles_x, int tiles_y)
 {
-    extern __shared__ float sg[];
-    const TileGeom t = tile_geom(a, rz, ry, rx, tiles_x, tiles_y);
+    extern __shared__ float sv[];
+    int bx, by, bz;
+    block_tile(tiles_x, tiles_y, bx, by, bz);
+    argext_tile<T>(a, code, op, se, rz, ry, rx, bx, by, bz, sv);
+}
+
+// Batched: in = volume, aux = code volume (written).
+template <typename T>
+__global__ __launch_bounds__(kGT) void argext_batched_kernel(BatchDesc d, int op, int se, int rz, int ry, int rx)
+{
+    extern __shared__ float sv[];
+    const int total = d.prefix[d.n_crops];
+    for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
+        int c, bx, by, bz;
+        batch_item(d, w, c, bx, by, bz);
+        const ChunkArgs a = crop_args(d.c[c]);
+        argext_tile<T>(a, static_cast<uint16_t *>(const_cast<void *>(d.c[c].aux)), op, se, rz, ry, rx, bx, by, bz,
+                       sv);
+        lds_barrier();
+    }
+}
+
+// gin over the output region of `a` (gin laid out like a.out); g and code
+// laid out like the input region of `a` (a.in describes them: in = g).
+__device__ __forceinline__ void gather_tile(const ChunkArgs &a, const uint16_t *code, int se, int rz, int ry, int rx,
+                                            int bx, int by, int bz, float *sg)
+{
+    const TileGeom t = tile_geom(a, rz, ry, rx, bx, by, bz);
     const int n_lds = t.hz * t.hy * t.hx;
     uint32_t *sc = reinterpret_cast<uint32_t *>(sg + n_lds);
     const float *g = static_cast<const float *>(a.in);
@@ -168,15 +197,15 @@ __global__ __launch_bounds__(kGT) void gather_kernel(ChunkArgs a, const uint16_t
         sg[e] = g[off];
         sc[e] = inside ? (uint32_t)code[off] : 0xffffffffu;
     }
-    __syncthreads();
+    lds_barrier();
     const int tx = threadIdx.x % kGX, ty = threadIdx.x / kGX;
     const int64_t gx = t.x0 + tx, gy = t.y0 + ty;
     const int64_t xend = a.out_o[2] + a.out_e[2], yend = a.out_o[1] + a.out_e[1];
     const int64_t zend = a.out_o[0] + a.out_e[0];
-    if (gx >= xend || gy >= yend) return;
+    const bool active = gx < xend && gy < yend;
     const int wx = 2 * rx + 1, wyx = (2 * ry + 1) * wx;
     float *gin = static_cast<float *>(a.out);
-    for (int tz = 0; tz < kGZ; ++tz) {
+    for (int tz = 0; active && tz < kGZ; ++tz) {
         const int64_t gz = t.z0 + tz;
         if (gz >= zend) break;
         float sum = 0.f;
@@ -189,6 +218,29 @@ __global__ __launch_bounds__(kGT) void gather_kernel(ChunkArgs a, const uint16_t
                     if (sc[e] == (uint32_t)((dz + rz) * wyx + (dy + ry) * wx + (dx + rx))) sum += sg[e];
                 }
         gin[(gz - a.out_o[0]) * a.out_sz + (gy - a.out_o[1]) * a.out_sy + (gx - a.out_o[2])] = sum;
+    }
+}
+
+__global__ __launch_bounds__(kGT) void gather_kernel(ChunkArgs a, const uint16_t *code, int se, int rz, int ry,
+                                                     int rx, int tiles_x, int tiles_y)
+{
+    extern __shared__ float sg[];
+    int bx, by, bz;
+    block_tile(tiles_x, tiles_y, bx, by, bz);
+    gather_tile(a, code, se, rz, ry, rx, bx, by, bz, sg);
+}
+
+// Batched: in = upstream gradient, aux = codes, out = grad_in.
+__global__ __launch_bounds__(kGT) void gather_batched_kernel(BatchDesc d, int se, int rz, int ry, int rx)
+{
+    extern __shared__ float sg[];
+    const int total = d.prefix[d.n_crops];
+    for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
+        int c, bx, by, bz;
+        batch_item(d, w, c, bx, by, bz);
+        const ChunkArgs a = crop_args(d.c[c]);
+        gather_tile(a, static_cast<const uint16_t *>(d.c[c].aux), se, rz, ry, rx, bx, by, bz, sg);
+        lds_barrier();
     }
 }
 
@@ -236,6 +288,33 @@ bool launch_gather(const ChunkArgs &a, const uint16_t *code, int se, const int r
     const size_t lds = 8 * (size_t)(kGZ + 2 * r[0]) * (kGY + 2 * r[1]) * (kGX + 2 * r[2]);
     hipLaunchKernelGGL(gather_kernel, dim3((uint32_t)blocks), dim3(kGT), lds, s, a, code, se, r[0], r[1], r[2], tx,
                        ty);
+    return true;
+}
+
+bool launch_argext_batched(const BatchDesc &d0, harpia_dtype t, int op, int se, const int r[3], hipStream_t s)
+{
+    if (!morph_grad_supported(r) || t != HARPIA_F32) return false;
+    BatchDesc d = d0;
+    batch_layout(d, kGX, kGY, kGZ);
+    const size_t lds = sizeof(float) * (kGZ + 2 * r[0]) * (kGY + 2 * r[1]) * (kGX + 2 * r[2]);
+    const int64_t cap = resident_blocks(argext_batched_kernel<float>, kGT, lds);
+    const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < 8192 ? cap : 8192);
+    if (grid > 0)
+        hipLaunchKernelGGL((argext_batched_kernel<float>), dim3((uint32_t)grid), dim3(kGT), lds, s, d, op, se, r[0],
+                           r[1], r[2]);
+    return true;
+}
+
+bool launch_gather_batched(const BatchDesc &d0, int se, const int r[3], hipStream_t s)
+{
+    if (!morph_grad_supported(r)) return false;
+    BatchDesc d = d0;
+    batch_layout(d, kGX, kGY, kGZ);
+    const size_t lds = 8 * (size_t)(kGZ + 2 * r[0]) * (kGY + 2 * r[1]) * (kGX + 2 * r[2]);
+    const int64_t cap = resident_blocks(gather_batched_kernel, kGT, lds);
+    const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < 8192 ? cap : 8192);
+    if (grid > 0)
+        hipLaunchKernelGGL(gather_batched_kernel, dim3((uint32_t)grid), dim3(kGT), lds, s, d, se, r[0], r[1], r[2]);
     return true;
 }
 

@@ -2,6 +2,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "batch.h"
 
 namespace harpia {
 
@@ -37,6 +38,15 @@ bool launch_morph_ex(const ChunkArgs &a, harpia_dtype t, const MorphSpec &m, boo
     case HARPIA_BF16: return morph_run<bf16_t>(a, m, both, out2, thr_f, s);
     }
     return false;
+}
+
+template <typename T>
+bool morph_batched_run(const BatchDesc &d, int op, int se, int r, bool both, hipStream_t s);
+
+bool launch_morph_batched(const BatchDesc &d, harpia_dtype t, int op, int se, int r, bool both, hipStream_t s)
+{
+    if (t != HARPIA_F32) return false;
+    return morph_batched_run<float>(d, op, se, r, both, s);
 }
 
 bool launch_morph(const ChunkArgs &a, harpia_dtype t, const MorphSpec &m, hipStream_t s)

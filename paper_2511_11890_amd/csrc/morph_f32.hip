@@ -3,4 +3,5 @@
 
 namespace harpia {
 template bool morph_run<float>(const ChunkArgs &, const MorphSpec &, bool, const Region *, float, hipStream_t);
+template bool morph_batched_run<float>(const BatchDesc &, int, int, int, bool, hipStream_t);
 }  // namespace harpia

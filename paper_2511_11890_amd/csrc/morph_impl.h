@@ -33,6 +33,7 @@
 #include <utility>
 
 #include "common.h"
+#include "batch.h"
 
 namespace harpia {
 
@@ -54,8 +55,6 @@ namespace morph_detail {
 
 constexpr int kNT = 256;
 constexpr int kMaxFastR = 4;
-constexpr int kDepth = 3;     // input slices in flight per thread (prefetch ring)
-constexpr int kBinDepth = 1;  // binary: words are packed on load, so no ring
 
 constexpr int isqrt_c(int v)
 {
@@ -88,25 +87,15 @@ struct Grid {
     int64_t blocks;
 };
 
-inline Grid make_grid(const ChunkArgs &a, int TX, int TY, int R)
+inline Grid make_grid(const ChunkArgs &a, int TX, int TY, int R, int64_t capacity)
 {
     Grid g;
     g.tiles_x = (int)((a.out_e[2] + TX - 1) / TX);
     g.tiles_y = (int)((a.out_e[1] + TY - 1) / TY);
     const int64_t tiles = (int64_t)g.tiles_x * g.tiles_y;
-    int64_t zlen = a.out_e[0];
-    const int64_t want = 4096;
-    if (tiles < want) {
-        const int64_t nzc = (want + tiles - 1) / tiles;
-        zlen = (a.out_e[0] + nzc - 1) / nzc;
-        const int64_t min_len = 8 * R > 32 ? 8 * R : 32;
-        if (zlen < min_len) zlen = min_len;
-    } else if (zlen > 256) {
-        zlen = 256;
-    }
-    if (zlen > a.out_e[0]) zlen = a.out_e[0];
-    g.zlen = (int)zlen;
-    g.blocks = tiles * ((a.out_e[0] + zlen - 1) / zlen);
+    const int64_t nzc = z_ranges(a.out_e[0], tiles, capacity, R);
+    g.zlen = (int)((a.out_e[0] + nzc - 1) / nzc);
+    g.blocks = tiles * ((a.out_e[0] + g.zlen - 1) / g.zlen);
     return g;
 }
 
@@ -121,8 +110,8 @@ struct Out2 {
 };
 
 template <typename T, int SE, int R, bool BOTH>
-__global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float sign, int tiles_x, int tiles_y,
-                                                   int zlen)
+__device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, float sign, int zlen, int bx, int by,
+                                          int bz)
 {
     using S = Shape<SE, R>;
     constexpr int P = 2 * R + 1;
@@ -140,11 +129,6 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
     __shared__ __attribute__((aligned(16))) float sH[NM][S::NL][PH * kGTX];
 
     const int tid = threadIdx.x;
-    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int bx = (int)(b % (uint32_t)tiles_x);
-    const int by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
-    const int bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
-
     const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
     const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1];
     const int64_t x0 = xbeg + (int64_t)bx * kGTX;
@@ -172,15 +156,19 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
         }
     }
 
+    const int64_t s0 = zo0 - R;
+    const int nsteps = (int)(zo1 - zo0) + 2 * R;
     const T *in = static_cast<const T *>(a.in);
-    // Prefetch ring: at the start of step i, pf[k] holds slice i + k, as
-    // raw loaded values (converted when staged, so the loads stay in flight).
-    T pf[kDepth][NLD];
-    auto fetch = [&](int64_t s, T(&dst)[NLD]) __attribute__((always_inline)) {
-        const T *base = in + (reflect_index(s, a.n[0]) - a.in_o[0]) * a.in_sz;
+    // The next slice's raw values (converted when staged, so the loads stay
+    // in flight through a whole step).  The fetch is unconditional: past the
+    // last slice it re-reads that slice, which is never used.
+    T pf[NLD];
+    auto fetch = [&](int j) __attribute__((always_inline)) {
+        j = j < nsteps ? j : nsteps - 1;
+        const T *base = in + (reflect_index(s0 + j, a.n[0]) - a.in_o[0]) * a.in_sz;
 #pragma unroll
         for (int i = 0; i < NLD; ++i)
-            if (i < NLD - 1 || tid + i * kNT < PSZ) dst[i] = base[off[i]];
+            if (i < NLD - 1 || tid + i * kNT < PSZ) pf[i] = base[off[i]];
     };
 
     const int qrow = tid / (kGTX / 4);
@@ -199,32 +187,49 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[m][j][c] = 0.f;
 
-    const int64_t s0 = zo0 - R;
-    const int nsteps = (int)(zo1 - zo0) + 2 * R;
-#pragma unroll
-    for (int d = 0; d < kDepth; ++d)
-        if (d < nsteps) fetch(s0 + d, pf[d]);
+    fetch(0);
 
-    for (int base = 0; base < nsteps; base += P) {
+    // Step i (0 .. nsteps): store the output completed by step i - 1; if
+    // i < nsteps, filter slice i.  Stores follow the next slice's fetch so
+    // that the next staging waits only for work issued a step earlier.
+    for (int base = 0; base <= nsteps; base += P) {
         static_for<P>([&](auto U) {
             constexpr int u = decltype(U)::value;
             const int i = base + u;
+            if (i > nsteps) return;
+            if (i < nsteps) {
+                // 1. stage (with the sign flip of a single erosion), fetch the next
+#pragma unroll
+                for (int k = 0; k < NLD; ++k)
+                    if (k < NLD - 1 || tid + k * kNT < PSZ)
+                        sP[lds[k]] = BOTH ? to_f32(pf[k]) : sign * to_f32(pf[k]);
+                fetch(i + 1);
+            }
+            if (i >= 1 && i - 1 >= 2 * R && nvalid > 0) {
+                constexpr int sl = (u - 1 - R + 2 * P) % P;
+                const int64_t zl = s0 + (i - 1) - R - a.out_o[0];
+                if constexpr (BOTH) {
+                    // out = erosion (min), out2 = dilation (max)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (q < nvalid) {
+                            outp[zl * a.out_sz + q] = from_f32<T>(acc[1][sl][q]);
+                            outp2[zl * o2.sz + q] = from_f32<T>(acc[0][sl][q]);
+                        }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (q < nvalid) outp[zl * a.out_sz + q] = from_f32<T>(sign * acc[0][sl][q]);
+                }
+            }
             if (i >= nsteps) return;
-
-            // 1. stage (with the sign flip of a single erosion), advance the ring
-#pragma unroll
-            for (int k = 0; k < NLD; ++k)
-                if (k < NLD - 1 || tid + k * kNT < PSZ)
-                    sP[lds[k]] = BOTH ? to_f32(pf[0][k]) : sign * to_f32(pf[0][k]);
-#pragma unroll
-            for (int d = 0; d + 1 < kDepth; ++d)
-#pragma unroll
-                for (int k = 0; k < NLD; ++k) pf[d][k] = pf[d + 1][k];
-            if (i + kDepth < nsteps) fetch(s0 + i + kDepth, pf[kDepth - 1]);
-            __syncthreads();
+            lds_barrier();
 
             // 2. stage A: x-run extrema of every level on all patch rows
-            for (int it = tid; it < NA; it += kNT) {
+#pragma unroll
+            for (int itk = 0; itk < (NA + kNT - 1) / kNT; ++itk) {
+                const int it = tid + itk * kNT;
+                if (itk == (NA + kNT - 1) / kNT - 1 && it >= NA) continue;
                 const int row = it / (kGTX / 4);
                 const int c0 = (it % (kGTX / 4)) * 4;
                 float v[NV4 * 4];
@@ -261,7 +266,7 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
                             make_float4(res[l][0], res[l][1], res[l][2], res[l][3]);
                 }
             }
-            __syncthreads();
+            lds_barrier();
 
             // 3. stage B: in-plane disc of each z-class (4 columns), fed
             // straight into the z ring slots of the offsets of that class
@@ -299,24 +304,34 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
                     });
                 });
             }
-            if (i >= 2 * R && nvalid > 0) {
-                constexpr int sl = (u - R + 2 * P) % P;
-                const int64_t zl = s0 + i - R - a.out_o[0];
-                if constexpr (BOTH) {
-                    // out = erosion (min), out2 = dilation (max)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (q < nvalid) {
-                            outp[zl * a.out_sz + q] = from_f32<T>(acc[1][sl][q]);
-                            outp2[zl * o2.sz + q] = from_f32<T>(acc[0][sl][q]);
-                        }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (q < nvalid) outp[zl * a.out_sz + q] = from_f32<T>(sign * acc[0][sl][q]);
-                }
-            }
         });
+    }
+}
+
+template <typename T, int SE, int R, bool BOTH>
+__global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float sign, int tiles_x, int tiles_y,
+                                                   int zlen)
+{
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = (int)(b % (uint32_t)tiles_x);
+    const int by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
+    const int bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
+    gray_tile<T, SE, R, BOTH>(a, o2, sign, zlen, bx, by, bz);
+}
+
+// Persistent batched grayscale morphology (in -> out, aux -> second output
+// of a "both" step; the same element for every crop).
+template <typename T, int SE, int R, bool BOTH>
+__global__ __launch_bounds__(kNT) void gray_batched_kernel(BatchDesc d, float sign)
+{
+    const int total = d.prefix[d.n_crops];
+    for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
+        int c, bx, by, bz;
+        batch_item(d, w, c, bx, by, bz);
+        const ChunkArgs a = crop_args(d.c[c]);
+        const Out2 o2{const_cast<void *>(d.c[c].aux), a.out_sy, a.out_sz};
+        gray_tile<T, SE, R, BOTH>(a, o2, sign, d.c[c].zlen, bx, by, bz);
+        lds_barrier();
     }
 }
 
@@ -408,11 +423,14 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
         }
     }
 
+    const int64_t s0 = zo0 - R;
+    const int nsteps = (int)(zo1 - zo0) + 2 * R;
     const Tin *in = static_cast<const Tin *>(a.in);
-    // Prefetch ring: at the start of step i, pf[k] holds slice i + k.
-    uint32_t pf[kBinDepth][NLW];
-    auto fetch = [&](int64_t s, uint32_t(&dst)[NLW]) __attribute__((always_inline)) {
-        const Tin *base = in + (reflect_index(s, a.n[0]) - a.in_o[0]) * a.in_sz;
+    // The next slice, packed on load (unconditional fetch, clamped at the end).
+    uint32_t pf[NLW];
+    auto fetch = [&](int j) __attribute__((always_inline)) {
+        j = j < nsteps ? j : nsteps - 1;
+        const Tin *base = in + (reflect_index(s0 + j, a.n[0]) - a.in_o[0]) * a.in_sz;
 #pragma unroll
         for (int i = 0; i < NLW; ++i) {
             if (i < NLW - 1 || tid + i * kNT < NWI) {
@@ -433,7 +451,7 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
                         wv |= binarise(base[ly * a.in_sy + lx], thr, use_thr) << (8 * j);
                     }
                 }
-                dst[i] = wv;
+                pf[i] = wv;
             }
         }
     };
@@ -454,30 +472,42 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[m][j][c] = 0u;
 
-    const int64_t s0 = zo0 - R;
-    const int nsteps = (int)(zo1 - zo0) + 2 * R;
-#pragma unroll
-    for (int d = 0; d < kBinDepth; ++d)
-        if (d < nsteps) fetch(s0 + d, pf[d]);
+    fetch(0);
 
-    for (int base = 0; base < nsteps; base += P) {
+    for (int base = 0; base <= nsteps; base += P) {
         static_for<P>([&](auto U) {
             constexpr int u = decltype(U)::value;
             const int i = base + u;
+            if (i > nsteps) return;
+            if (i < nsteps) {
+#pragma unroll
+                for (int k = 0; k < NLW; ++k)
+                    if (k < NLW - 1 || tid + k * kNT < NWI) sP[tid + k * kNT] = BOTH ? pf[k] : (pf[k] ^ fmask);
+                fetch(i + 1);
+            }
+            if (i >= 1 && i - 1 >= 2 * R && nvalid > 0) {
+                constexpr int sl = (u - 1 - R + 2 * P) % P;
+                const int64_t zl = s0 + (i - 1) - R - a.out_o[0];
+                if constexpr (BOTH) {
+                    emit16(outp + zl * a.out_sz, make_uint4(acc[1][sl][0], acc[1][sl][1], acc[1][sl][2], acc[1][sl][3]),
+                           nvalid);
+                    emit16(outp2 + zl * o2.sz, make_uint4(acc[0][sl][0], acc[0][sl][1], acc[0][sl][2], acc[0][sl][3]),
+                           nvalid);
+                } else {
+                    emit16(outp + zl * a.out_sz,
+                           make_uint4(acc[0][sl][0] ^ fmask, acc[0][sl][1] ^ fmask, acc[0][sl][2] ^ fmask,
+                                      acc[0][sl][3] ^ fmask),
+                           nvalid);
+                }
+            }
             if (i >= nsteps) return;
-
-#pragma unroll
-            for (int k = 0; k < NLW; ++k)
-                if (k < NLW - 1 || tid + k * kNT < NWI) sP[tid + k * kNT] = BOTH ? pf[0][k] : (pf[0][k] ^ fmask);
-#pragma unroll
-            for (int d = 0; d + 1 < kBinDepth; ++d)
-#pragma unroll
-                for (int k = 0; k < NLW; ++k) pf[d][k] = pf[d + 1][k];
-            if (i + kBinDepth < nsteps) fetch(s0 + i + kBinDepth, pf[kBinDepth - 1]);
-            __syncthreads();
+            lds_barrier();
 
             // stage A: word-level x runs (OR for m = 0, AND for m = 1)
-            for (int it = tid; it < NA; it += kNT) {
+#pragma unroll
+            for (int itk = 0; itk < (NA + kNT - 1) / kNT; ++itk) {
+                const int it = tid + itk * kNT;
+                if (itk == (NA + kNT - 1) / kNT - 1 && it >= NA) continue;
                 const int row = it / kBW, w = it - (it / kBW) * kBW;
                 const uint32_t wl = sP[row * kBPW + w];
                 const uint32_t wc = sP[row * kBPW + w + 1];
@@ -496,7 +526,7 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
                     });
                 }
             }
-            __syncthreads();
+            lds_barrier();
 
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
@@ -527,21 +557,6 @@ __global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint3
                         }
                     });
                 });
-            }
-            if (i >= 2 * R && nvalid > 0) {
-                constexpr int sl = (u - R + 2 * P) % P;
-                const int64_t zl = s0 + i - R - a.out_o[0];
-                if constexpr (BOTH) {
-                    emit16(outp + zl * a.out_sz, make_uint4(acc[1][sl][0], acc[1][sl][1], acc[1][sl][2], acc[1][sl][3]),
-                           nvalid);
-                    emit16(outp2 + zl * o2.sz, make_uint4(acc[0][sl][0], acc[0][sl][1], acc[0][sl][2], acc[0][sl][3]),
-                           nvalid);
-                } else {
-                    emit16(outp + zl * a.out_sz,
-                           make_uint4(acc[0][sl][0] ^ fmask, acc[0][sl][1] ^ fmask, acc[0][sl][2] ^ fmask,
-                                      acc[0][sl][3] ^ fmask),
-                           nvalid);
-                }
             }
         });
     }
@@ -603,12 +618,14 @@ template <typename T, int SE, int R, bool BOTH>
 void launch_fast(const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float thr_f, hipStream_t s)
 {
     if (m.binary) {
-        const Grid g = make_grid(a, kBTX, kBTY, R);
+        static const int64_t cap = resident_blocks(binary_kernel<T, SE, R, BOTH>, kNT);
+        const Grid g = make_grid(a, kBTX, kBTY, R, cap);
         hipLaunchKernelGGL((binary_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, o2,
                            (uint32_t)(m.op == 0 ? 1u : 0u), thr_f, (int)m.has_threshold, g.tiles_x, g.tiles_y,
                            g.zlen);
     } else {
-        const Grid g = make_grid(a, kGTX, kGTY, R);
+        static const int64_t cap = resident_blocks(gray_kernel<T, SE, R, BOTH>, kNT);
+        const Grid g = make_grid(a, kGTX, kGTY, R, cap);
         hipLaunchKernelGGL((gray_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, o2,
                            m.op == 0 ? -1.f : 1.f, g.tiles_x, g.tiles_y, g.zlen);
     }
@@ -665,6 +682,45 @@ template <typename T>
 bool morph_run(const ChunkArgs &a, const MorphSpec &m, bool both, const Region *out2, float thr_f, hipStream_t s)
 {
     return morph_detail::run<T>(a, m, both, out2, thr_f, s);
+}
+
+namespace morph_detail {
+
+template <typename T, int SE, int R, bool BOTH>
+void launch_gray_batched(BatchDesc d, float sign, hipStream_t s)
+{
+    static const int64_t cap = resident_blocks(gray_batched_kernel<T, SE, R, BOTH>, kNT);
+    batch_layout(d, kGTX, kGTY, 32);
+    const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < 8192 ? cap : 8192);
+    if (grid > 0)
+        hipLaunchKernelGGL((gray_batched_kernel<T, SE, R, BOTH>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, sign);
+}
+
+template <typename T, int SE, bool BOTH>
+bool gray_batched_r(int r, const BatchDesc &d, float sign, hipStream_t s)
+{
+    switch (r) {
+    case 1: launch_gray_batched<T, SE, 1, BOTH>(d, sign, s); return true;
+    case 2: launch_gray_batched<T, SE, 2, BOTH>(d, sign, s); return true;
+    case 3: launch_gray_batched<T, SE, 3, BOTH>(d, sign, s); return true;
+    case 4: launch_gray_batched<T, SE, 4, BOTH>(d, sign, s); return true;
+    default: return false;
+    }
+}
+
+}  // namespace morph_detail
+
+// Grayscale batched erosion (op 0) / dilation (op 1), or both (aux = dilation).
+template <typename T>
+bool morph_batched_run(const BatchDesc &d, int op, int se, int r, bool both, hipStream_t s)
+{
+    using namespace morph_detail;
+    const float sign = (!both && op == 0) ? -1.f : 1.f;
+    if (se == HARPIA_SE_BOX)
+        return both ? gray_batched_r<T, HARPIA_SE_BOX, true>(r, d, sign, s)
+                    : gray_batched_r<T, HARPIA_SE_BOX, false>(r, d, sign, s);
+    return both ? gray_batched_r<T, HARPIA_SE_BALL, true>(r, d, sign, s)
+                : gray_batched_r<T, HARPIA_SE_BALL, false>(r, d, sign, s);
 }
 
 }  // namespace harpia
