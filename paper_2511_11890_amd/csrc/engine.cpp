@@ -658,6 +658,7 @@ void plan_chunks(const int64_t n[3], const int32_t halo[3], const int64_t chunk[
         p.grid[a] = (n[a] + core[a] - 1) / core[a];
         total *= p.grid[a];
     }
+    if (nb > total) nb = (int)total;  // no more buffer sets than chunks
     p.n_chunks = total;
     p.n_buffers = nb;
     p.device_bytes = chunk_bytes(cost, core, n) * (size_t)nb;
