@@ -241,7 +241,7 @@ harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t,
  * the element's offsets inside the volume (ties go to the earliest offset):
  *   grad_in[j] = sum of grad_out[p] over the outputs p that chose j,
  * summed in a fixed order (no atomics; deterministic).  grad_out and grad_in
- * are float32.  Radii up to 8 per axis. */
+ * are float32.  Box radii up to 8 per axis; ball radius up to 4. */
 harpia_status harpia_morph3d_backward(const void *in, harpia_dtype t,
                                       const void *grad_out, void *grad_in,
                                       const int64_t shape[3],

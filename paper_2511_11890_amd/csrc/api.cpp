@@ -432,7 +432,8 @@ harpia_status harpia_morph3d_backward(const void *in, harpia_dtype t, const void
         check_exec(ex);
         if (op != HARPIA_ERODE && op != HARPIA_DILATE) fail(HARPIA_ERR_ARG, "unknown morphology op");
         const MorphArgs m = check_morph(t, se, radius, std::nan(""), HARPIA_BORDER_REFLECT, nullptr);
-        if (!morph_grad_supported(m.r)) fail(HARPIA_ERR_UNSUPPORTED, "morphology gradient radius above 8");
+        if (!morph_grad_supported((int)se, m.r))
+            fail(HARPIA_ERR_UNSUPPORTED, "morphology gradient: box radii above 8 or ball radius above 4");
         const int64_t nv = voxels(shape);
         check_alias(grad_out, nv * 4, grad_in, nv * 4);
         check_alias(in, nv * dtype_size(t), grad_in, nv * 4);
@@ -618,7 +619,8 @@ harpia_status harpia_morph3d_backward_batched(const harpia_crop *crops, int32_t 
         check_exec(ex);
         if (op != HARPIA_ERODE && op != HARPIA_DILATE) fail(HARPIA_ERR_ARG, "unknown morphology op");
         const MorphArgs m = check_morph(HARPIA_F32, se, radius, std::nan(""), HARPIA_BORDER_REFLECT, nullptr);
-        if (!morph_grad_supported(m.r)) fail(HARPIA_ERR_UNSUPPORTED, "morphology gradient radius above 8");
+        if (!morph_grad_supported((int)se, m.r))
+            fail(HARPIA_ERR_UNSUPPORTED, "morphology gradient: box radii above 8 or ball radius above 4");
         check_crops(crops, n_crops, true, true, true);
         const size_t need = harpia_batch_workspace_bytes(crops, n_crops);
         if (!workspace || workspace_bytes < need) fail(HARPIA_ERR_ARG, "workspace too small");

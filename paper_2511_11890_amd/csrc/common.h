@@ -253,7 +253,7 @@ void launch_reduce_f64(const float *partials, int64_t n, double *out, bool accum
 int64_t launch_dot_partials(const Region &a, const Region &b, float *partials, int64_t max_blocks, hipStream_t s);
 // Erosion / dilation subgradient: codes of the first extremum, then the
 // gather of the upstream gradient.  Radii up to 8 per axis.
-bool morph_grad_supported(const int r[3]);
+bool morph_grad_supported(int se, const int r[3]);
 bool launch_argext(const ChunkArgs &a, harpia_dtype t, int op, int se, const int r[3], uint16_t *code,
                    hipStream_t s);
 bool launch_gather(const ChunkArgs &a, const uint16_t *code, int se, const int r[3], hipStream_t s);

@@ -6,13 +6,32 @@
 // to the voxel that supplied the extremum.  Ties are broken by taking the
 // first extremum in lexicographic (dz, dy, dx) order over the offsets of the
 // element that fall inside the volume (a later offset wins only when it is
-// strictly better).  Two kernels:
+// strictly better).  Inputs holding NaN have no defined subgradient.
+//
+// Box element (separable).  Over a box clipped to the volume the offsets
+// form a product set, and the lexicographically first extremum factorises
+// exactly into three 1D first-extremum stages applied innermost first: at
+// every voxel s the row stage picks dx among s + dx e_x, at every voxel q
+// the plane stage picks dy among the row extrema at q + dy e_y, and at every
+// output p the volume stage picks dz among the plane extrema at p + dz e_z.
+// Each stage keeps the earliest offset among equal values, so the composed
+// pick is the smallest (dz, dy, dx) among the maxima.  Erosion maximises the
+// negated values (exact in f32).  Two z-streaming kernels:
+//   argext_box: code[v] = xsel(v) | ysel(v) << 5 | zsel(v) << 10 (each field
+//               offset + radius) -- the three stages' picks at voxel v;
+//   gather_box: the adjoint of the composition, stage by stage in reverse
+//               order: G1 = Z^T g (pushed into a ring of z accumulators),
+//               G2 = Y^T G1, grad_in = X^T G2.  Every sum runs in a fixed
+//               order (G1 by source slice, G2 by dy, grad_in by dx), so the
+//               result does not depend on the tiling or the batching.
+//
+// Ball element (brute force over the element's offsets):
 //   argext: code[p] = index of the chosen offset in the element's bounding
 //           box, (dz + rz) (2ry + 1) (2rx + 1) + (dy + ry) (2rx + 1) + dx + rx;
 //   gather: gin[j] = sum over offsets o of the element, in lexicographic
 //           order, of g[j - o] where code[j - o] names o.
-// Both stage a halo-padded 3D tile in LDS.  The gather is a deterministic
-// sum in a fixed order (no atomics).
+// Both stage a halo-padded 3D tile in LDS.  The gathers are deterministic
+// sums (no atomics).
 //
 // sigma-gradient: per-block FP32 partials (from the fused Gaussian's dot
 // epilogue, or from dot_partials_kernel) are reduced in FP64 in a fixed
@@ -244,6 +263,304 @@ __global__ __launch_bounds__(kGT) void gather_batched_kernel(BatchDesc d, int se
     }
 }
 
+// ------------------------------------------------------------ box, separable
+
+constexpr int kSepThreads = 256;
+
+__device__ __forceinline__ int wrap_slot(int s, int w) { return s < 0 ? s + w : (s >= w ? s - w : s); }
+
+// LDS layout of argext_box: input slice (HY x SX), row extrema (HY x TX),
+// ring of plane extrema (W x TY x TX) and their xy picks (u16), row picks (u8).
+__host__ __device__ inline size_t argext_box_lds(int tx, int ty, int rz, int ry, int rx)
+{
+    const size_t hy = ty + 2 * ry, sx = tx + 2 * rx, w = 2 * rz + 1;
+    return hy * sx * 4 + hy * tx * 4 + w * ty * tx * 6 + hy * tx;
+}
+
+// LDS layout of gather_box: ring of z accumulators (W x HY x SX), the
+// y-adjoint slice (TY x SX) and the ring of codes (W x HY x SX, u16).
+__host__ __device__ inline size_t gather_box_lds(int tx, int ty, int rz, int ry, int rx)
+{
+    const size_t hy = ty + 2 * ry, sx = tx + 2 * rx, w = 2 * rz + 1;
+    return w * hy * sx * 6 + ty * sx * 4;
+}
+
+// Work items: (crop, TX x TY column, z range of zlen outputs).  in = volume,
+// aux = code volume (written).
+template <typename T>
+__global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, int erode, int rz, int ry, int rx,
+                                                                 int TX, int TY)
+{
+    extern __shared__ float lds[];
+    const int SX = TX + 2 * rx, HY = TY + 2 * ry, W = 2 * rz + 1, P = TY * TX;
+    float *sv = lds;
+    float *rv = sv + HY * SX;
+    float *pv = rv + HY * TX;
+    uint16_t *pc = reinterpret_cast<uint16_t *>(pv + W * P);
+    uint8_t *rs = reinterpret_cast<uint8_t *>(pc + W * P);
+    const int tid = threadIdx.x;
+    const int total = d.prefix[d.n_crops];
+    for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
+        int c, bx, by, bz;
+        batch_item(d, w, c, bx, by, bz);
+        const BatchCrop &k = d.c[c];
+        const T *in = static_cast<const T *>(k.in);
+        uint16_t *code = static_cast<uint16_t *>(const_cast<void *>(k.aux));
+        const int nz = k.n[0], ny = k.n[1], nx = k.n[2];
+        const int x0 = bx * TX, y0 = by * TY;
+        const int z_lo = bz * k.zlen, z_hi = min(nz, z_lo + k.zlen);
+        const int t0 = z_lo - rz;
+        int slot = ((t0 % W) + W) % W;  // ring slot of slice t
+        for (int t = t0; t < z_hi + rz; ++t) {
+            const bool has_in = t >= 0 && t < nz;
+            if (has_in) {
+                // stage slice t (clamped positions are never picked)
+                for (int e = tid; e < HY * SX; e += kSepThreads) {
+                    const int ly = e / SX, lx = e - ly * SX;
+                    const int gy = min(max(y0 - ry + ly, 0), ny - 1), gx = min(max(x0 - rx + lx, 0), nx - 1);
+                    const float v = to_f32(in[((int64_t)t * ny + gy) * nx + gx]);
+                    sv[e] = erode ? -v : v;
+                }
+            }
+            lds_barrier();
+            if (has_in) {
+                // row stage at every row of the halo'd column
+                for (int e = tid; e < HY * TX; e += kSepThreads) {
+                    const int ly = e / TX, x = e - ly * TX, gx = x0 + x, gy = y0 - ry + ly;
+                    if (gx >= nx || gy < 0 || gy >= ny) continue;
+                    const int lo = max(-rx, -gx), hi = min(rx, nx - 1 - gx);
+                    const float *row = sv + ly * SX + x + rx;
+                    float best = row[lo];
+                    int bi = lo;
+                    for (int dx = lo + 1; dx <= hi; ++dx) {
+                        const float v = row[dx];
+                        if (v > best) {
+                            best = v;
+                            bi = dx;
+                        }
+                    }
+                    rv[e] = best;
+                    rs[e] = (uint8_t)(bi + rx);
+                }
+            }
+            lds_barrier();
+            if (has_in) {
+                // plane stage; each thread keeps its own positions of the ring
+                for (int e = tid; e < P; e += kSepThreads) {
+                    const int y = e / TX, x = e - y * TX, gy = y0 + y;
+                    if (gy >= ny || x0 + x >= nx) continue;
+                    const int lo = max(-ry, -gy), hi = min(ry, ny - 1 - gy);
+                    const float *col = rv + (y + ry) * TX + x;
+                    float best = col[lo * TX];
+                    int bi = lo;
+                    for (int dy = lo + 1; dy <= hi; ++dy) {
+                        const float v = col[dy * TX];
+                        if (v > best) {
+                            best = v;
+                            bi = dy;
+                        }
+                    }
+                    pv[slot * P + e] = best;
+                    pc[slot * P + e] = (uint16_t)(rs[(y + ry) * TX + x] | (bi + ry) << 5);
+                }
+            }
+            const int zo = t - rz;
+            if (zo >= z_lo) {
+                // volume stage of output slice zo (reads only this thread's
+                // ring positions: no barrier needed)
+                const int so = wrap_slot(slot - rz, W);
+                const int lo = max(-rz, -zo), hi = min(rz, nz - 1 - zo);
+                for (int e = tid; e < P; e += kSepThreads) {
+                    const int y = e / TX, x = e - y * TX, gy = y0 + y, gx = x0 + x;
+                    if (gy >= ny || gx >= nx) continue;
+                    int sz = wrap_slot(so + lo, W);
+                    float best = pv[sz * P + e];
+                    int bi = lo;
+                    for (int dz = lo + 1; dz <= hi; ++dz) {
+                        sz = sz + 1 == W ? 0 : sz + 1;
+                        const float v = pv[sz * P + e];
+                        if (v > best) {
+                            best = v;
+                            bi = dz;
+                        }
+                    }
+                    code[((int64_t)zo * ny + gy) * nx + gx] = (uint16_t)(pc[so * P + e] | (bi + rz) << 10);
+                }
+            }
+            slot = slot + 1 == W ? 0 : slot + 1;
+        }
+        lds_barrier();
+    }
+}
+
+// Work items as in argext_box.  in = upstream gradient g, aux = codes,
+// out = grad_in.
+__global__ __launch_bounds__(kSepThreads) void gather_box_kernel(BatchDesc d, int rz, int ry, int rx, int TX, int TY)
+{
+    extern __shared__ float lds[];
+    const int SX = TX + 2 * rx, HY = TY + 2 * ry, W = 2 * rz + 1, H = HY * SX;
+    float *acc = lds;
+    float *g2 = acc + W * H;
+    uint16_t *cr = reinterpret_cast<uint16_t *>(g2 + TY * SX);
+    const int tid = threadIdx.x;
+    const int total = d.prefix[d.n_crops];
+    for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
+        int c, bx, by, bz;
+        batch_item(d, w, c, bx, by, bz);
+        const BatchCrop &k = d.c[c];
+        const float *g = static_cast<const float *>(k.in);
+        const uint16_t *code = static_cast<const uint16_t *>(k.aux);
+        float *gin = static_cast<float *>(k.out);
+        const int nz = k.n[0], ny = k.n[1], nx = k.n[2];
+        const int x0 = bx * TX, y0 = by * TY;
+        const int z_lo = bz * k.zlen, z_hi = min(nz, z_lo + k.zlen);
+        // the accumulator positions a thread clears are the ones it pushes to
+        for (int e = tid; e < H; e += kSepThreads)
+            for (int j = 0; j < W; ++j) acc[j * H + e] = 0.f;
+        const int t0 = z_lo - rz;
+        int slot = ((t0 % W) + W) % W;
+        for (int t = t0; t < z_hi + rz; ++t) {
+            if (t >= 0 && t < nz) {
+                // push slice t: G1[p + zsel(p)] += g[p] for outputs in range
+                for (int e = tid; e < H; e += kSepThreads) {
+                    const int ly = e / SX, lx = e - ly * SX, gy = y0 - ry + ly, gx = x0 - rx + lx;
+                    uint32_t cv = 0xffffu;
+                    if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
+                        const int64_t idx = ((int64_t)t * ny + gy) * nx + gx;
+                        cv = code[idx];
+                        const int dz = (int)(cv >> 10) - rz, q = t + dz;
+                        if (q >= z_lo && q < z_hi) acc[wrap_slot(slot + dz, W) * H + e] += g[idx];
+                    }
+                    cr[slot * H + e] = (uint16_t)cv;
+                }
+            }
+            lds_barrier();
+            const int qz = t - rz;
+            const int sq = wrap_slot(slot - rz, W);
+            if (qz >= z_lo) {
+                // G2 = Y^T G1 over the x-halo'd rows of the tile
+                const float *a = acc + sq * H;
+                const uint16_t *cq = cr + sq * H;
+                for (int e = tid; e < TY * SX; e += kSepThreads) {
+                    const int y = e / SX, lx = e - y * SX;
+                    float sum = 0.f;
+                    for (int dy = -ry; dy <= ry; ++dy) {
+                        const int q = (y + ry - dy) * SX + lx;
+                        if (((cq[q] >> 5) & 31) == dy + ry) sum += a[q];
+                    }
+                    g2[e] = sum;
+                }
+            }
+            lds_barrier();
+            if (qz >= z_lo) {
+                // grad_in = X^T G2, then release this slice's accumulators
+                const uint16_t *cq = cr + sq * H;
+                for (int e = tid; e < TY * TX; e += kSepThreads) {
+                    const int y = e / TX, x = e - y * TX, gy = y0 + y, gx = x0 + x;
+                    if (gy >= ny || gx >= nx) continue;
+                    float sum = 0.f;
+                    for (int dx = -rx; dx <= rx; ++dx) {
+                        const int q = x + rx - dx;
+                        if ((cq[(y + ry) * SX + q] & 31) == dx + rx) sum += g2[y * SX + q];
+                    }
+                    gin[((int64_t)qz * ny + gy) * nx + gx] = sum;
+                }
+                for (int e = tid; e < H; e += kSepThreads) acc[sq * H + e] = 0.f;
+            }
+            slot = slot + 1 == W ? 0 : slot + 1;
+        }
+        lds_barrier();
+    }
+}
+
+struct SepTile {
+    int tx, ty;
+};
+
+// Largest column tile whose LDS fits 64 KiB (the kernels are written for
+// any tile; wide tiles cut the halo re-reads).
+template <class F>
+bool pick_sep_tile(F lds_of, SepTile &t, size_t &lds)
+{
+    static const SepTile cand[] = {{64, 8}, {64, 4}, {32, 4}, {32, 2}, {16, 2}, {16, 1}};
+    for (const SepTile &c : cand) {
+        const size_t b = lds_of(c.tx, c.ty);
+        if (b <= 65536) {
+            t = c;
+            lds = b;
+            return true;
+        }
+    }
+    return false;
+}
+
+// z-range length: whole-depth columns when there are enough of them to fill
+// the device several times over, else shorter ranges (each range re-reads
+// 2 rz halo slices).
+inline int sep_zlen(const BatchDesc &d, int tx, int ty, int rz, int64_t capacity)
+{
+    int zlen = 256;
+    const int floor_len = 8 * rz > 16 ? 8 * rz : 16;
+    while (zlen > floor_len) {
+        int64_t items = 0;
+        for (int c = 0; c < d.n_crops; ++c)
+            items += (int64_t)((d.c[c].n[2] + tx - 1) / tx) * ((d.c[c].n[1] + ty - 1) / ty) *
+                     ((d.c[c].n[0] + zlen - 1) / zlen);
+        if (items >= 4 * capacity) break;
+        zlen /= 2;
+    }
+    return zlen;
+}
+
+template <typename T>
+bool argext_box_run(BatchDesc d, int op, const int r[3], hipStream_t s)
+{
+    SepTile tile;
+    size_t lds;
+    if (!pick_sep_tile([&](int tx, int ty) { return argext_box_lds(tx, ty, r[0], r[1], r[2]); }, tile, lds))
+        return false;
+    const int64_t cap = resident_blocks(argext_box_kernel<T>, kSepThreads, lds);
+    batch_layout(d, tile.tx, tile.ty, sep_zlen(d, tile.tx, tile.ty, r[0], cap));
+    const int64_t grid = batch_grid(d.prefix[d.n_crops], cap);
+    if (grid > 0)
+        hipLaunchKernelGGL((argext_box_kernel<T>), dim3((uint32_t)grid), dim3(kSepThreads), lds, s, d,
+                           op == HARPIA_ERODE ? 1 : 0, r[0], r[1], r[2], tile.tx, tile.ty);
+    return true;
+}
+
+bool gather_box_run(BatchDesc d, const int r[3], hipStream_t s)
+{
+    SepTile tile;
+    size_t lds;
+    if (!pick_sep_tile([&](int tx, int ty) { return gather_box_lds(tx, ty, r[0], r[1], r[2]); }, tile, lds))
+        return false;
+    const int64_t cap = resident_blocks(gather_box_kernel, kSepThreads, lds);
+    batch_layout(d, tile.tx, tile.ty, sep_zlen(d, tile.tx, tile.ty, r[0], cap));
+    const int64_t grid = batch_grid(d.prefix[d.n_crops], cap);
+    if (grid > 0)
+        hipLaunchKernelGGL(gather_box_kernel, dim3((uint32_t)grid), dim3(kSepThreads), lds, s, d, r[0], r[1], r[2],
+                           tile.tx, tile.ty);
+    return true;
+}
+
+// One whole volume as a one-crop batch.
+inline BatchDesc single_desc(const void *in, void *out, const void *aux, const int64_t n[3])
+{
+    BatchDesc d;
+    d.n_crops = 1;
+    d.c[0].in = in;
+    d.c[0].out = out;
+    d.c[0].aux = aux;
+    for (int i = 0; i < 3; ++i) d.c[0].n[i] = (int32_t)n[i];
+    return d;
+}
+
+// Brute-force LDS of the ball kernels (float values + u32 codes for the gather).
+inline size_t ball_lds(const int r[3], size_t per_voxel)
+{
+    return per_voxel * (size_t)(kGZ + 2 * r[0]) * (kGY + 2 * r[1]) * (kGX + 2 * r[2]);
+}
+
 int64_t tiles_of(const ChunkArgs &a, int &tiles_x, int &tiles_y)
 {
     tiles_x = (int)((a.out_e[2] + kGX - 1) / kGX);
@@ -255,15 +572,41 @@ int64_t tiles_of(const ChunkArgs &a, int &tiles_x, int &tiles_y)
 
 constexpr int kMaxGradRadius = 8;
 
-bool morph_grad_supported(const int r[3]) { return r[0] <= kMaxGradRadius && r[1] <= kMaxGradRadius && r[2] <= kMaxGradRadius; }
+// Box: radii up to 8 per axis (the separable kernels' LDS fits for all of
+// them).  Ball: the brute-force tile must fit 64 KiB of LDS, radius <= 4.
+bool morph_grad_supported(int se, const int r[3])
+{
+    if (se == HARPIA_SE_BOX)
+        return r[0] <= kMaxGradRadius && r[1] <= kMaxGradRadius && r[2] <= kMaxGradRadius;
+    return ball_lds(r, 8) <= 65536;
+}
+
+static bool whole_volume(const ChunkArgs &a)
+{
+    for (int i = 0; i < 3; ++i)
+        if (a.in_o[i] != 0 || a.out_o[i] != 0 || a.out_e[i] != a.n[i] || a.n[i] > (1 << 24)) return false;
+    return a.in_sy == a.n[2] && a.out_sy == a.n[2] && a.in_sz == a.n[1] * a.n[2] && a.out_sz == a.n[1] * a.n[2];
+}
 
 bool launch_argext(const ChunkArgs &a, harpia_dtype t, int op, int se, const int r[3], uint16_t *code, hipStream_t s)
 {
-    if (!morph_grad_supported(r)) return false;
+    if (!morph_grad_supported(se, r)) return false;
+    if (se == HARPIA_SE_BOX) {
+        if (!whole_volume(a)) return false;
+        const BatchDesc d = single_desc(a.in, nullptr, code, a.n);
+        switch (t) {
+        case HARPIA_F32: return argext_box_run<float>(d, op, r, s);
+        case HARPIA_U16: return argext_box_run<uint16_t>(d, op, r, s);
+        case HARPIA_U8: return argext_box_run<uint8_t>(d, op, r, s);
+        case HARPIA_F16: return argext_box_run<_Float16>(d, op, r, s);
+        case HARPIA_BF16: return argext_box_run<bf16_t>(d, op, r, s);
+        }
+        return false;
+    }
     int tx, ty;
     const int64_t blocks = tiles_of(a, tx, ty);
     if (blocks == 0) return true;
-    const size_t lds = sizeof(float) * (kGZ + 2 * r[0]) * (kGY + 2 * r[1]) * (kGX + 2 * r[2]);
+    const size_t lds = ball_lds(r, sizeof(float));
 #define HARPIA_ARG(DT, T)                                                                                     \
     if (t == DT) {                                                                                            \
         hipLaunchKernelGGL((argext_kernel<T>), dim3((uint32_t)blocks), dim3(kGT), lds, s, a, code, op, se, r[0], \
@@ -281,11 +624,15 @@ bool launch_argext(const ChunkArgs &a, harpia_dtype t, int op, int se, const int
 
 bool launch_gather(const ChunkArgs &a, const uint16_t *code, int se, const int r[3], hipStream_t s)
 {
-    if (!morph_grad_supported(r)) return false;
+    if (!morph_grad_supported(se, r)) return false;
+    if (se == HARPIA_SE_BOX) {
+        if (!whole_volume(a)) return false;
+        return gather_box_run(single_desc(a.in, a.out, code, a.n), r, s);
+    }
     int tx, ty;
     const int64_t blocks = tiles_of(a, tx, ty);
     if (blocks == 0) return true;
-    const size_t lds = 8 * (size_t)(kGZ + 2 * r[0]) * (kGY + 2 * r[1]) * (kGX + 2 * r[2]);
+    const size_t lds = ball_lds(r, 8);
     hipLaunchKernelGGL(gather_kernel, dim3((uint32_t)blocks), dim3(kGT), lds, s, a, code, se, r[0], r[1], r[2], tx,
                        ty);
     return true;
@@ -293,10 +640,11 @@ bool launch_gather(const ChunkArgs &a, const uint16_t *code, int se, const int r
 
 bool launch_argext_batched(const BatchDesc &d0, harpia_dtype t, int op, int se, const int r[3], hipStream_t s)
 {
-    if (!morph_grad_supported(r) || t != HARPIA_F32) return false;
+    if (!morph_grad_supported(se, r) || t != HARPIA_F32) return false;
+    if (se == HARPIA_SE_BOX) return argext_box_run<float>(d0, op, r, s);
     BatchDesc d = d0;
     batch_layout(d, kGX, kGY, kGZ);
-    const size_t lds = sizeof(float) * (kGZ + 2 * r[0]) * (kGY + 2 * r[1]) * (kGX + 2 * r[2]);
+    const size_t lds = ball_lds(r, sizeof(float));
     const int64_t cap = resident_blocks(argext_batched_kernel<float>, kGT, lds);
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < 8192 ? cap : 8192);
     if (grid > 0)
@@ -307,10 +655,11 @@ bool launch_argext_batched(const BatchDesc &d0, harpia_dtype t, int op, int se, 
 
 bool launch_gather_batched(const BatchDesc &d0, int se, const int r[3], hipStream_t s)
 {
-    if (!morph_grad_supported(r)) return false;
+    if (!morph_grad_supported(se, r)) return false;
+    if (se == HARPIA_SE_BOX) return gather_box_run(d0, r, s);
     BatchDesc d = d0;
     batch_layout(d, kGX, kGY, kGZ);
-    const size_t lds = 8 * (size_t)(kGZ + 2 * r[0]) * (kGY + 2 * r[1]) * (kGX + 2 * r[2]);
+    const size_t lds = ball_lds(r, 8);
     const int64_t cap = resident_blocks(gather_batched_kernel, kGT, lds);
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < 8192 ? cap : 8192);
     if (grid > 0)

@@ -67,7 +67,8 @@ def test_sigma_gradient_host_pointer_and_deterministic(dev):
 
 
 @pytest.mark.parametrize("op", ["erode", "dilate"])
-@pytest.mark.parametrize("se,r", [("box", 1), ("box", 2), ("ball", 2), ("ball", 3), ("box", (1, 2, 0))])
+@pytest.mark.parametrize("se,r", [("box", 1), ("box", 2), ("ball", 2), ("ball", 3), ("box", (1, 2, 0)),
+                                  ("box", (3, 1, 4)), ("box", 8), ("ball", 4)])
 def test_morph_gradient_ties_exact(dev, op, se, r):
     # integer data with many ties and integer upstream gradients: the sums
     # are exact in FP32, so the tie rule must match the oracle bit for bit
@@ -81,13 +82,36 @@ def test_morph_gradient_ties_exact(dev, op, se, r):
     np.testing.assert_array_equal(to_np64(gi), want)
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.uint16, torch.bfloat16])
+def test_morph_gradient_limits(dev):
+    v = torch.zeros((8, 9, 10), device=dev)
+    with pytest.raises(h.HarpiaError):
+        h.morph_backward(v, v, "dilate", "ball", 5)
+    with pytest.raises(h.HarpiaError):
+        h.morph_backward(v, v, "dilate", "box", 9)
+
+
+def test_morph_gradient_large_ragged(dev):
+    # several tiles in x and y, several z ranges, ragged tails on every axis
+    shape = (150, 77, 203)
+    rng = np.random.default_rng(41)
+    v = rng.integers(0, 5, size=shape).astype(np.float32)
+    g = rng.integers(-3, 4, size=shape).astype(np.float32)
+    for op in ("erode", "dilate"):
+        gi = h.morph_backward(torch.from_numpy(v).to(dev), torch.from_numpy(g).to(dev), op, "box", (2, 3, 1))
+        torch.cuda.synchronize()
+        want = oracle.morph3d_backward(v.astype(np.float64), g.astype(np.float64), op, "box", (2, 3, 1))
+        np.testing.assert_array_equal(to_np64(gi), want)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.uint16, torch.bfloat16, torch.uint8, torch.float16])
 def test_morph_gradient_dtypes(dev, dtype):
     shape = (17, 29, 90)
     v = phantoms.porous(shape, seed=37)
     if dtype == torch.uint16:
         v = phantoms.porous_u16(shape, seed=37)
-    elif dtype == torch.bfloat16:
+    elif dtype == torch.uint8:
+        v = (phantoms.porous_u16(shape, seed=37).to(torch.int32) >> 8).to(torch.uint8)
+    elif dtype in (torch.bfloat16, torch.float16):
         v = torch.clamp(v, 0, 1).to(dtype)
     g = phantoms.gaussian_noise(shape, seed=38)
     gi = h.morph_backward(v.to(dev), g.to(dev), "dilate", "box", 2)
