@@ -22,6 +22,7 @@ learnable-sigma Gaussian + box-5 dilation, forward + backward in one graph).
 from __future__ import annotations
 
 import argparse
+import csv
 import glob
 import hashlib
 import json
@@ -32,6 +33,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# tiles chosen by the library's autotuner for these workloads on MI355X
+# (written by `bench.py --tune`, loaded by every other run)
+TILES = os.path.join(ROOT, "paper_2511_11890_amd", "tiles_mi355x.txt")
+
 METRIC = "GVox/s plain FP32 vs BF16+fused fwd/bwd filter at stated err; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 # fp32 vector peak of the chip: 256 CU x 4 SIMD x 16 lanes x 2 (packed dual
@@ -39,8 +44,18 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 KERNEL_SOURCES = {
-    "gauss": ["paper_2511_11890_amd/csrc/gauss_impl.h", "paper_2511_11890_amd/csrc/gauss_f32.hip"],
-    "morph": ["paper_2511_11890_amd/csrc/morph_impl.h", "paper_2511_11890_amd/csrc/morph_f32.hip"],
+    "gauss": ["paper_2511_11890_amd/csrc/common.h", "paper_2511_11890_amd/csrc/gauss_grid.h",
+              "paper_2511_11890_amd/csrc/gauss_impl.h", "paper_2511_11890_amd/csrc/gauss_f32.hip"],
+    "morph": ["paper_2511_11890_amd/csrc/common.h", "paper_2511_11890_amd/csrc/morph_impl.h",
+              "paper_2511_11890_amd/csrc/morph_f32.hip"],
+}
+
+# kernel-name fragments of the resident workload's ops (f32, fused kernels)
+RESIDENT_KERNELS = {
+    "gauss_s1": ("gauss", "gauss_fused_kernel<float, float, 3,"),
+    "gauss_s2": ("gauss", "gauss_fused_kernel<float, float, 6,"),
+    "gauss_s4": ("gauss", "gauss_fused_kernel<float, float, 12,"),
+    "erode_dilate_ball3": ("morph", "gray_kernel<float, 1, 3, true>"),
 }
 
 
@@ -52,17 +67,103 @@ def sources_sha(kind: str) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(op_name: str, kind: str, launches_voxels: int):
+def traffic_for(op_name: str, kind: str, size: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
+    it was taken on the current kernel source at this size; else None."""
     for path in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.json")):
         try:
-            d = json.load(open(path))
-        except Exception:
+            with open(path) as f:
+                d = json.load(f)
+        except (OSError, ValueError):
             continue
-        if d.get("op") == op_name and d.get("source_sha") == sources_sha(kind):
-            return d.get("hbm_bytes_per_launch")
+        op = d.get("ops", {}).get(op_name)
+        if op and d.get("size") == size and d.get("source_sha", {}).get(kind) == sources_sha(kind):
+            return op.get("hbm_bytes_per_launch")
     return None
+
+
+def tiles_load(path: str) -> dict:
+    """Load the autotuner's recorded tiles, if the file exists."""
+    import paper_2511_11890_amd as h
+
+    if not os.path.exists(path):
+        return {"source": "heuristic"}
+    h.tune_load(path)
+    return {"source": os.path.relpath(path, ROOT), "entries": h.tune_entries()}
+
+
+def tiles_merge_save(path: str) -> dict:
+    """Merge the tiles recorded in this process into the tile file."""
+    import paper_2511_11890_amd as h
+
+    mine = os.path.join(os.path.dirname(path), ".tiles_new.txt")
+    h.tune_save(mine)
+    if os.path.exists(path):
+        h.tune_load(path)   # older entries ...
+        h.tune_load(mine)   # ... overridden by this run's
+    h.tune_save(path)
+    os.remove(mine)
+    return {"source": "autotuned in this run, saved to " + os.path.relpath(path, ROOT),
+            "entries": h.tune_entries()}
+
+
+def _csv_rows(root: str, suffix: str):
+    for path in sorted(glob.glob(os.path.join(root, "**", "*" + suffix), recursive=True)):
+        with open(path) as f:
+            yield from csv.DictReader(f)
+
+
+def _short(name: str) -> str:
+    s = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return s.split("(")[0]
+
+
+def stats_summary(root: str, command: str, title: str) -> str:
+    """Markdown table of a `rocprofv3 --kernel-trace --stats --output-format
+    csv` run (its kernel_stats.csv under `root`)."""
+    lines = ["# %s" % title, "", "command: `%s`" % command, "",
+             "| kernel | calls | avg us | min us | max us | total ms | % |", "|---|---|---|---|---|---|---|"]
+    for row in _csv_rows(root, "kernel_stats.csv"):
+        lines.append("| %s | %s | %.1f | %.1f | %.1f | %.2f | %.1f |" % (
+            _short(row["Name"]), row["Calls"], float(row["AverageNs"]) / 1e3, float(row["MinNs"]) / 1e3,
+            float(row["MaxNs"]) / 1e3, float(row["TotalDurationNs"]) / 1e6, float(row["Percentage"])))
+    return "\n".join(lines) + "\n"
+
+
+def traffic_summary(fetch_root: str, write_root: str, size: int, commands) -> dict:
+    """HBM bytes per launch of the resident ops from two `rocprofv3 --pmc`
+    runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
+    `bench.py --copy-ref`.  Each counter is scaled by what it reads for the
+    plain device copy of the volume in the same run (the largest copy
+    dispatch: 4 * size^3 bytes read and written)."""
+    vox = size ** 3
+    copy_kib = 4.0 * vox / 1024.0
+    out = {"size": size, "commands": list(commands), "source_sha": {k: sources_sha(k) for k in KERNEL_SOURCES},
+           "copy_ref": {}, "ops": {}}
+    per_op = {op: {} for op in RESIDENT_KERNELS}
+    for counter, root in (("FETCH_SIZE", fetch_root), ("WRITE_SIZE", write_root)):
+        rows = [r for r in _csv_rows(root, "counter_collection.csv") if r["Counter_Name"] == counter]
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        if not copies:
+            raise SystemExit("no copy dispatch in %s" % root)
+        ref = max(copies)
+        scale = copy_kib / ref
+        out["copy_ref"][counter] = {"kib": ref, "expected_kib": copy_kib, "scale": round(scale, 4)}
+        for op, (_, pat) in RESIDENT_KERNELS.items():
+            vals = [float(r["Counter_Value"]) for r in rows if pat in r["Kernel_Name"]]
+            if vals:
+                per_op[op][counter] = (sum(vals) / len(vals), len(vals), scale)
+    for op, d in per_op.items():
+        if len(d) != 2:
+            continue
+        nout = 2 if op.startswith("erode_dilate") else 1
+        fetch = d["FETCH_SIZE"][0] * d["FETCH_SIZE"][2] * 1024.0
+        write = d["WRITE_SIZE"][0] * d["WRITE_SIZE"][2] * 1024.0
+        alg = 4.0 * vox * (1 + nout)
+        out["ops"][op] = {"fetch_kib_raw": round(d["FETCH_SIZE"][0], 1), "write_kib_raw": round(d["WRITE_SIZE"][0], 1),
+                          "dispatches": d["FETCH_SIZE"][1], "hbm_bytes_per_launch": int(fetch + write),
+                          "alg_bytes_per_launch": int(alg), "traffic_over_alg": round((fetch + write) / alg, 4)}
+    return out
 
 
 def cpu_baseline(v_dev, sample_slices: int = 24):
@@ -119,6 +220,16 @@ def run_resident(args):
     ops = [("gauss_s1", lambda: op_gauss(1.0), 3), ("gauss_s2", lambda: op_gauss(2.0), 6),
            ("gauss_s4", lambda: op_gauss(4.0), 12), ("erode_dilate_ball3", op_morph, 3)]
     outputs_per_step = 5
+
+    if args.tune:
+        tuned = {}
+        for s in (1.0, 2.0, 4.0):
+            tuned["gauss_s%g" % s] = h.autotune_gaussian(v, s, out=outs[s])
+        tuned["erode_dilate_ball3"] = h.autotune_erode_dilate(v, "ball", 3, ero=ero, dil=dil)
+        tiles = tiles_merge_save(args.tiles)
+        tiles["report"] = tuned
+    else:
+        tiles = tiles_load(args.tiles)
 
     for _ in range(args.warmup):
         for _, fn, _ in ops:
@@ -179,8 +290,7 @@ def run_resident(args):
         roof = {"bound": "hbm", "kernel": dom, "achieved": dd["hbm_gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dd["hbm_gbs"] / HBM_PEAK_GBS, 4),
                 "per_launch": {"bytes": alg_bytes, "ms": dd["ms"]}}
-    tb = traffic_for(dom, kind, vox)
-    roof["traffic"] = tb
+    roof["traffic"] = traffic_for(dom, kind, n)
 
     value = outputs_per_step * vox / (ms_step / 1000.0) / 1e9
     line = {"metric": METRIC, "value": round(value, 2), "unit": "GVox/s", "n_gpus": 1,
@@ -190,7 +300,7 @@ def run_resident(args):
             "config": {"workload": "resident %d^3 float32 porous phantom: Gaussian sigma 1,2,4 + "
                                    "grayscale erode+dilate ball r=3" % n, "voxels": vox,
                        "outputs_per_step": outputs_per_step},
-            "roofline": roof, "ops": per_op, "hbm_copy_gbs": round(copy_gbs, 1)}
+            "roofline": roof, "ops": per_op, "hbm_copy_gbs": round(copy_gbs, 1), "tiles": tiles}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(v)
     return line
@@ -293,6 +403,12 @@ def run_batched(args):
     cs = [phantoms.gaussian_noise(x.shape, seed=100 + i, device=dev) for i, x in enumerate(xs)]
     vox = sum(x.numel() for x in xs)
     b = h.GaussDilateBatch(xs, 1.5, "box", 2)
+    if args.tune:
+        tuned = b.autotune()
+        tiles = tiles_merge_save(args.tiles)
+        tiles["report"] = tuned
+    else:
+        tiles = tiles_load(args.tiles)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -336,7 +452,8 @@ def run_batched(args):
             "config": {"workload": "batched: 64 float32 crops, extents U[64,256], Gaussian sigma 1.5 (learnable) "
                                    "+ box-5 dilation, forward + backward per step, one graph replay",
                        "voxels": vox, "crops": len(xs)},
-            "ops": dict(phases, graph_ms=round(ms, 3), hbm_frac_alg20=round(alg / ms / 1e6 / HBM_PEAK_GBS, 4))}
+            "ops": dict(phases, graph_ms=round(ms, 3), hbm_frac_alg20=round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)),
+            "tiles": tiles}
 
 
 def main():
@@ -349,7 +466,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one plain device copy of the volume (counter reference)")
+    ap.add_argument("--tune", action="store_true",
+                    help="resident / batched: run the autotuner on the ops first and merge its tiles into --tiles")
+    ap.add_argument("--tiles", default=TILES, help="tile file of the autotuner (loaded if present)")
+    ap.add_argument("--stats-summary", nargs=3, metavar=("CSV_DIR", "COMMAND", "TITLE"),
+                    help="print a markdown summary of a rocprofv3 --stats csv run and exit (no GPU)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "FETCH_CMD", "WRITE_CMD"),
+                    help="print the HBM traffic JSON of two rocprofv3 --pmc runs and exit (no GPU)")
     args = ap.parse_args()
+    if args.stats_summary:
+        print(stats_summary(*args.stats_summary), end="")
+        return
+    if args.traffic_summary:
+        fr, wr, fc, wc = args.traffic_summary
+        print(json.dumps(traffic_summary(fr, wr, args.size or 1024, (fc, wc)), indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs no multi-GPU path (one process, one device). "
               "Run with --gpus 1.", file=sys.stderr)

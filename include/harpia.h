@@ -310,6 +310,74 @@ harpia_status harpia_morph3d_backward_batched(const harpia_crop *crops,
                                               size_t workspace_bytes,
                                               const harpia_exec *ex);
 
+/* ------------------------------------------------------------------
+ * Autotuner (an extension beyond the paper).  Each call below runs the
+ * named operation on the caller's own operands once per tile candidate of
+ * the kernels it launches (z-range split of the resident kernels; slices
+ * per work item and column tile of the batched kernels), times the
+ * candidates with HIP events on ex->stream (one warm-up, then `reps` timed
+ * runs each; 0 -> 3), and records the fastest per (kernel, radius, element
+ * type, extents or crop list).  Every later call in this process with the
+ * same workload launches the recorded tile; a candidate is kept only if it
+ * beats the library's own heuristic by 2 %.  Outputs and scratch operands
+ * are overwritten.  Synchronous: ex->stream is idle on return.  Not for use
+ * under graph capture.
+ * ------------------------------------------------------------------ */
+
+typedef struct harpia_tune_entry {
+    char kernel[24];       /* kernel family */
+    int32_t tile[3];       /* chosen {tx, ty, tz}; zeros = the heuristic */
+    int32_t candidates;    /* candidates timed */
+    float ms_heuristic;    /* mean time of the call with the heuristic tile */
+    float ms_best;         /* mean time with the chosen tile */
+} harpia_tune_entry;
+
+typedef struct harpia_tune_report {
+    int32_t n;
+    harpia_tune_entry e[8];
+} harpia_tune_report;
+
+/* Tunes the fused Gaussian of harpia_gaussian3d on these operands (device
+ * pointers).  report may be NULL. */
+harpia_status harpia_autotune_gaussian3d(const void *in, harpia_dtype in_t,
+                                         void *out, harpia_dtype out_t,
+                                         const int64_t shape[3],
+                                         const double sigma[3],
+                                         double truncate, int32_t reps,
+                                         const harpia_exec *ex,
+                                         harpia_tune_report *report);
+
+/* Tunes the morphology kernel of harpia_erode_dilate3d (grayscale, or
+ * binary when a threshold or HARPIA_F_BINARY is given). */
+harpia_status harpia_autotune_erode_dilate3d(const void *in, void *out_erode,
+                                             void *out_dilate, harpia_dtype t,
+                                             const int64_t shape[3],
+                                             harpia_se se,
+                                             const int32_t radius[3],
+                                             double threshold, int32_t reps,
+                                             const harpia_exec *ex,
+                                             harpia_tune_report *report);
+
+/* Tunes the batched kernels of a Gaussian -> dilation pipeline with its
+ * gradients: harpia_gaussian3d_batched, harpia_morph3d_batched (dilation),
+ * harpia_morph3d_backward_batched and the sigma-gradient of
+ * harpia_gaussian3d_backward_batched.  Per crop: in = the Gaussian's input,
+ * out and aux = two scratch volumes of the crop's shape (overwritten).
+ * gauss_radius: the radii held fixed (equal, 1..12); workspace as for the
+ * batched backward calls. */
+harpia_status harpia_autotune_gauss_dilate_batched(
+    const harpia_crop *crops, int32_t n_crops, const double sigma[3],
+    const int32_t gauss_radius[3], harpia_se se, const int32_t morph_radius[3],
+    void *workspace, size_t workspace_bytes, int32_t reps,
+    const harpia_exec *ex, harpia_tune_report *report);
+
+/* Recorded tiles: forget all, count, or save to / merge from a text file
+ * ("harpia-tune 1" then one "key tx ty tz" line per workload). */
+harpia_status harpia_tune_clear(void);
+int64_t harpia_tune_entries(void);
+harpia_status harpia_tune_save(const char *path);
+harpia_status harpia_tune_load(const char *path);
+
 #ifdef __cplusplus
 }
 #endif

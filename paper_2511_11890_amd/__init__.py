@@ -17,7 +17,8 @@ from ._lib import HarpiaError, harpia_plan, harpia_stats
 __all__ = ["gaussian", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
            "plan", "gauss_radius", "version", "HarpiaError", "harpia_stats", "Exec",
            "gaussian_backward", "morph_backward", "GaussianFn", "MorphFn", "GaussDilateFn",
-           "gaussian_batched", "morph_batched", "GaussDilateBatch"]
+           "gaussian_batched", "morph_batched", "GaussDilateBatch", "autotune_gaussian",
+           "autotune_erode_dilate", "tune_clear", "tune_entries", "tune_save", "tune_load"]
 
 
 def _torch():
@@ -470,6 +471,7 @@ class GaussDilateBatch:
         torch = _torch()
         self.xs = xs
         self.sigma = float(sigma)
+        self.truncate = float(truncate)
         self.r = gauss_radius(self.sigma, truncate)
         self.se, self.mr = se, radius
         self.ys = [torch.empty_like(x) for x in xs]
@@ -486,7 +488,8 @@ class GaussDilateBatch:
     def forward(self):
         lib, n, st = _lib.load(), len(self.xs), _lib.make_exec(stream=_stream())
         s3 = _lib.f64_3((self.sigma,) * 3)
-        _lib.check(lib.harpia_gaussian3d_batched(self._c_fwd_g, n, _lib.HARPIA_F32, _lib.HARPIA_F32, s3, 3.0, st))
+        _lib.check(lib.harpia_gaussian3d_batched(self._c_fwd_g, n, _lib.HARPIA_F32, _lib.HARPIA_F32, s3,
+                                                 self.truncate, st))
         _lib.check(lib.harpia_morph3d_batched(self._c_fwd_d, n, _lib.HARPIA_F32, _lib.HARPIA_DILATE,
                                               {"box": 0, "ball": 1}[self.se], _lib.i32_3(_triple(self.mr, int)),
                                               st))
@@ -504,13 +507,70 @@ class GaussDilateBatch:
         r3 = _lib.i32_3((self.r,) * 3)
         ws, wsb = self.workspace.data_ptr(), self.workspace.numel()
         # recompute y instead of keeping it from the forward
-        _lib.check(lib.harpia_gaussian3d_batched(self._c_fwd_g, n, _lib.HARPIA_F32, _lib.HARPIA_F32, s3, 3.0, st))
+        _lib.check(lib.harpia_gaussian3d_batched(self._c_fwd_g, n, _lib.HARPIA_F32, _lib.HARPIA_F32, s3,
+                                                 self.truncate, st))
         _lib.check(lib.harpia_morph3d_backward_batched(self._c_bwd_m, n, _lib.HARPIA_DILATE,
                                                        {"box": 0, "ball": 1}[self.se],
                                                        _lib.i32_3(_triple(self.mr, int)), ws, wsb, st))
         _lib.check(lib.harpia_gaussian3d_backward_batched(self._c_bwd_g, n, s3, r3, self.gsigma.data_ptr(), ws,
                                                           wsb, st))
         return self.gxs, self.gsigma
+
+    def autotune(self, reps: int = 3):
+        """Pick the tiles of every batched kernel of this pipeline on these
+        crops (the library's autotuner; y and g_y buffers are used as
+        scratch).  Returns the tuner's report, one dict per kernel."""
+        lib, n, st = _lib.load(), len(self.xs), _lib.make_exec(stream=_stream())
+        c = _lib.crops([(x, y, gy) for x, y, gy in zip(self.xs, self.ys, self.gys)])
+        rep = _lib.harpia_tune_report()
+        _lib.check(lib.harpia_autotune_gauss_dilate_batched(
+            c, n, _lib.f64_3((self.sigma,) * 3), _lib.i32_3((self.r,) * 3), {"box": 0, "ball": 1}[self.se],
+            _lib.i32_3(_triple(self.mr, int)), self.workspace.data_ptr(), self.workspace.numel(), int(reps), st,
+            _ctypes.byref(rep)))
+        return rep.entries()
+
+
+def autotune_gaussian(x, sigma, out=None, truncate: float = 3.0, reps: int = 3):
+    """Autotune the fused Gaussian on this device-resident volume (out is
+    overwritten); later calls with the same shape, dtype and radius use the
+    chosen z split.  Returns the tuner's report."""
+    torch = _torch()
+    out = torch.empty_like(x) if out is None else out
+    rep = _lib.harpia_tune_report()
+    _lib.check(_lib.load().harpia_autotune_gaussian3d(
+        x.data_ptr(), _dtype_code(x), out.data_ptr(), _dtype_code(out), _lib.i64_3(x.shape),
+        _lib.f64_3(_triple(sigma, float)), float(truncate), int(reps), _lib.make_exec(stream=_stream()),
+        _ctypes.byref(rep)))
+    return rep.entries()
+
+
+def autotune_erode_dilate(x, se: str = "ball", radius=1, ero=None, dil=None, reps: int = 3):
+    """Autotune the grayscale erosion+dilation kernel on this volume."""
+    torch = _torch()
+    ero = torch.empty_like(x) if ero is None else ero
+    dil = torch.empty_like(x) if dil is None else dil
+    rep = _lib.harpia_tune_report()
+    _lib.check(_lib.load().harpia_autotune_erode_dilate3d(
+        x.data_ptr(), ero.data_ptr(), dil.data_ptr(), _dtype_code(x), _lib.i64_3(x.shape),
+        {"box": 0, "ball": 1}[se], _lib.i32_3(_triple(radius, int)), float("nan"), int(reps),
+        _lib.make_exec(stream=_stream()), _ctypes.byref(rep)))
+    return rep.entries()
+
+
+def tune_clear():
+    _lib.check(_lib.load().harpia_tune_clear())
+
+
+def tune_entries() -> int:
+    return int(_lib.load().harpia_tune_entries())
+
+
+def tune_save(path: str):
+    _lib.check(_lib.load().harpia_tune_save(str(path).encode()))
+
+
+def tune_load(path: str):
+    _lib.check(_lib.load().harpia_tune_load(str(path).encode()))
 
 
 import ctypes as _ctypes  # noqa: E402

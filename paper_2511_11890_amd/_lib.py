@@ -61,6 +61,20 @@ class harpia_crop(ctypes.Structure):
                 ("shape", ctypes.c_int64 * 3)]
 
 
+class harpia_tune_entry(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 24), ("tile", ctypes.c_int32 * 3), ("candidates", ctypes.c_int32),
+                ("ms_heuristic", ctypes.c_float), ("ms_best", ctypes.c_float)]
+
+
+class harpia_tune_report(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("e", harpia_tune_entry * 8)]
+
+    def entries(self):
+        return [{"kernel": self.e[i].kernel.decode(), "tile": tuple(self.e[i].tile),
+                 "candidates": self.e[i].candidates, "ms_heuristic": round(self.e[i].ms_heuristic, 4),
+                 "ms_best": round(self.e[i].ms_best, 4)} for i in range(self.n)]
+
+
 class HarpiaError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
@@ -106,6 +120,20 @@ SIGNATURES = {
     "harpia_morph3d_backward_batched": (ctypes.c_int, [ctypes.POINTER(harpia_crop), ctypes.c_int32,
                                                        ctypes.c_int, ctypes.c_int, _I32_3, _vp,
                                                        ctypes.c_size_t, _ex]),
+    "harpia_autotune_gaussian3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _I64_3, _F64_3,
+                                                  ctypes.c_double, ctypes.c_int32, _ex,
+                                                  ctypes.POINTER(harpia_tune_report)]),
+    "harpia_autotune_erode_dilate3d": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _I64_3, ctypes.c_int, _I32_3,
+                                                      ctypes.c_double, ctypes.c_int32, _ex,
+                                                      ctypes.POINTER(harpia_tune_report)]),
+    "harpia_autotune_gauss_dilate_batched": (ctypes.c_int, [ctypes.POINTER(harpia_crop), ctypes.c_int32, _F64_3,
+                                                            _I32_3, ctypes.c_int, _I32_3, _vp, ctypes.c_size_t,
+                                                            ctypes.c_int32, _ex,
+                                                            ctypes.POINTER(harpia_tune_report)]),
+    "harpia_tune_clear": (ctypes.c_int, []),
+    "harpia_tune_entries": (ctypes.c_int64, []),
+    "harpia_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "harpia_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
 }
 
 _lib = None

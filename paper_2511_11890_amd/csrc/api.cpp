@@ -8,6 +8,7 @@
 
 #include "batch.h"
 #include "engine.h"
+#include "tune.h"
 
 namespace harpia {
 
@@ -648,6 +649,192 @@ harpia_status harpia_morph3d_backward_batched(const harpia_crop *crops, int32_t 
             if (!launch_gather_batched(d, (int)se, m.r, s)) fail(HARPIA_ERR_UNSUPPORTED, "no batched gather kernel");
             check_hip(hipGetLastError(), "kernel launch");
         }
+    });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+
+namespace harpia {
+namespace {
+
+// Runs `call` under every candidate tile of `fam`, keeps the fastest (a
+// candidate must beat the heuristic, candidate 0, by 2 %), records it for the
+// workloads the forced launches saw and appends a report entry.
+template <class Call>
+void tune_family(int fam, hipStream_t s, int reps, Call call, harpia_tune_report *rep)
+{
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    check_hip(hipEventCreate(&ev.a), "hipEventCreate");
+    check_hip(hipEventCreate(&ev.b), "hipEventCreate");
+    struct Unforce {
+        ~Unforce() { tune_force(0, -1); }
+    } unforce;
+    auto run = [&] {
+        const harpia_status st = call();
+        if (st != HARPIA_OK) fail(st, harpia_last_error());
+    };
+    const int n = tune_candidates(fam);
+    int best = 0;
+    float best_ms = 0.f, heur_ms = 0.f;
+    for (int i = 0; i < n; ++i) {
+        tune_force(fam, i);
+        run();  // warm-up
+        check_hip(hipEventRecord(ev.a, s), "hipEventRecord");
+        for (int k = 0; k < reps; ++k) run();
+        check_hip(hipEventRecord(ev.b, s), "hipEventRecord");
+        check_hip(hipEventSynchronize(ev.b), "hipEventSynchronize");
+        float ms = 0.f;
+        check_hip(hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
+        ms /= (float)reps;
+        if (i == 0) {
+            heur_ms = best_ms = ms;
+        } else if (ms < best_ms && ms < 0.98f * heur_ms) {
+            best_ms = ms;
+            best = i;
+        }
+    }
+    // one more run under the winner collects the workload keys to record
+    tune_force(fam, best);
+    run();
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    const Tile t = tune_candidate(fam, best);
+    tune_record_seen(fam, t);
+    if (rep && rep->n < (int32_t)(sizeof(rep->e) / sizeof(rep->e[0]))) {
+        harpia_tune_entry &e = rep->e[rep->n++];
+        std::memset(&e, 0, sizeof(e));
+        std::strncpy(e.kernel, tune_family_name(fam), sizeof(e.kernel) - 1);
+        e.tile[0] = t.tx;
+        e.tile[1] = t.ty;
+        e.tile[2] = t.tz;
+        e.candidates = n;
+        e.ms_heuristic = heur_ms;
+        e.ms_best = best_ms;
+    }
+}
+
+int tune_reps(int32_t reps) { return reps > 0 ? (reps < 100 ? reps : 100) : 3; }
+
+}  // namespace
+}  // namespace harpia
+
+extern "C" {
+
+using namespace harpia;
+
+harpia_status harpia_autotune_gaussian3d(const void *in, harpia_dtype in_t, void *out, harpia_dtype out_t,
+                                         const int64_t shape[3], const double sigma[3], double truncate,
+                                         int32_t reps, const harpia_exec *ex, harpia_tune_report *report)
+{
+    return guarded([&] {
+        if (report) report->n = 0;
+        if (!in || !out) fail(HARPIA_ERR_ARG, "in / out is NULL");
+        if (!is_device_pointer(in) || !is_device_pointer(out))
+            fail(HARPIA_ERR_UNSUPPORTED, "the autotuner runs on device-resident volumes");
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        tune_family(TF_GAUSS, s, tune_reps(reps), [&] {
+            return harpia_gaussian3d(in, in_t, out, out_t, shape, sigma, truncate, HARPIA_BORDER_REFLECT, ex);
+        }, report);
+    });
+}
+
+harpia_status harpia_autotune_erode_dilate3d(const void *in, void *out_erode, void *out_dilate, harpia_dtype t,
+                                             const int64_t shape[3], harpia_se se, const int32_t radius[3],
+                                             double threshold, int32_t reps, const harpia_exec *ex,
+                                             harpia_tune_report *report)
+{
+    return guarded([&] {
+        if (report) report->n = 0;
+        if (!in || !out_erode || !out_dilate) fail(HARPIA_ERR_ARG, "in / out is NULL");
+        if (!is_device_pointer(in) || !is_device_pointer(out_erode) || !is_device_pointer(out_dilate))
+            fail(HARPIA_ERR_UNSUPPORTED, "the autotuner runs on device-resident volumes");
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        const bool binary = !std::isnan(threshold) || (ex && (ex->flags & HARPIA_F_BINARY));
+        tune_family(binary ? TF_BINARY : TF_GRAY, s, tune_reps(reps), [&] {
+            return harpia_erode_dilate3d(in, out_erode, out_dilate, t, shape, se, radius, threshold,
+                                         HARPIA_BORDER_REFLECT, ex);
+        }, report);
+    });
+}
+
+harpia_status harpia_autotune_gauss_dilate_batched(const harpia_crop *crops, int32_t n_crops, const double sigma[3],
+                                                   const int32_t gauss_radius[3], harpia_se se,
+                                                   const int32_t morph_radius[3], void *workspace,
+                                                   size_t workspace_bytes, int32_t reps, const harpia_exec *ex,
+                                                   harpia_tune_report *report)
+{
+    return guarded([&] {
+        if (report) report->n = 0;
+        check_crops(crops, n_crops, true, true, true);
+        if (!sigma || !gauss_radius || !morph_radius) fail(HARPIA_ERR_ARG, "sigma / radius is NULL");
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        const int nr = std::max(1, tune_reps(reps) - 1);
+        // the Gaussian's truncate is chosen so that it resolves to gauss_radius
+        const double trunc = ((double)gauss_radius[0] + 0.25) / sigma[0];
+        std::vector<harpia_crop> fwd(crops, crops + n_crops), mor(n_crops), bwd(n_crops), dot(n_crops);
+        for (int32_t i = 0; i < n_crops; ++i) {
+            // x -> A (Gaussian), A -> B (dilation), subgradient of the
+            // dilation of A with upstream x into B, sigma-gradient with x and A
+            mor[i] = harpia_crop{crops[i].out, const_cast<void *>(crops[i].aux), nullptr, {0, 0, 0}};
+            bwd[i] = harpia_crop{crops[i].out, const_cast<void *>(crops[i].aux), crops[i].in, {0, 0, 0}};
+            dot[i] = harpia_crop{crops[i].in, nullptr, crops[i].out, {0, 0, 0}};
+            for (int a = 0; a < 3; ++a) mor[i].shape[a] = bwd[i].shape[a] = dot[i].shape[a] = crops[i].shape[a];
+        }
+        tune_family(TF_GAUSS_BATCHED, s, nr, [&] {
+            return harpia_gaussian3d_batched(fwd.data(), n_crops, HARPIA_F32, HARPIA_F32, sigma, trunc, ex);
+        }, report);
+        tune_family(TF_GRAY_BATCHED, s, nr, [&] {
+            return harpia_morph3d_batched(mor.data(), n_crops, HARPIA_F32, HARPIA_DILATE, se, morph_radius, ex);
+        }, report);
+        if (se == HARPIA_SE_BOX) {
+            for (int fam : {TF_ARGEXT_BOX, TF_GATHER_BOX})
+                tune_family(fam, s, nr, [&] {
+                    return harpia_morph3d_backward_batched(bwd.data(), n_crops, HARPIA_DILATE, se, morph_radius,
+                                                           workspace, workspace_bytes, ex);
+                }, report);
+        }
+        double *gs = nullptr;
+        check_hip(hipMalloc(&gs, 3 * sizeof(double)), "hipMalloc");
+        struct Free {
+            double *p;
+            ~Free() { (void)hipFree(p); }
+        } free_gs{gs};
+        tune_family(TF_GAUSS_DOT_BATCHED, s, nr, [&] {
+            return harpia_gaussian3d_backward_batched(dot.data(), n_crops, sigma, gauss_radius, gs, workspace,
+                                                      workspace_bytes, ex);
+        }, report);
+        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    });
+}
+
+harpia_status harpia_tune_clear(void)
+{
+    return guarded([&] { tune_clear(); });
+}
+
+int64_t harpia_tune_entries(void) { return tune_size(); }
+
+harpia_status harpia_tune_save(const char *path)
+{
+    return guarded([&] {
+        if (!path) fail(HARPIA_ERR_ARG, "path is NULL");
+        if (!tune_save(path)) fail(HARPIA_ERR_ARG, std::string("cannot write ") + path);
+    });
+}
+
+harpia_status harpia_tune_load(const char *path)
+{
+    return guarded([&] {
+        if (!path) fail(HARPIA_ERR_ARG, "path is NULL");
+        if (!tune_load(path)) fail(HARPIA_ERR_ARG, std::string("cannot read a tune cache from ") + path);
     });
 }
 

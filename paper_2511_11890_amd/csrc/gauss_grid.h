@@ -2,6 +2,8 @@
 // code that sizes the sigma-gradient partials).
 #pragma once
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace harpia {
@@ -19,13 +21,15 @@ struct FusedGrid {
 // partials: one per workgroup).
 constexpr int64_t kMaxZRanges = 64;
 
-inline FusedGrid fused_grid(const ChunkArgs &a, int R, int64_t capacity)
+// ranges > 0: split z into that many ranges (the autotuner's choice).
+inline FusedGrid fused_grid(const ChunkArgs &a, int R, int64_t capacity, int ranges = 0)
 {
     FusedGrid g;
     g.tiles_x = (int)((a.out_e[2] + kTX - 1) / kTX);
     g.tiles_y = (int)((a.out_e[1] + kTY - 1) / kTY);
     const int64_t tiles = (int64_t)g.tiles_x * g.tiles_y;
-    const int64_t nzc = z_ranges(a.out_e[0], tiles, capacity, R, kMaxZRanges);
+    int64_t nzc = z_ranges(a.out_e[0], tiles, capacity, R, kMaxZRanges);
+    if (ranges > 0) nzc = std::min<int64_t>(std::min<int64_t>(ranges, a.out_e[0]), kMaxZRanges);
     g.zlen = (int)((a.out_e[0] + nzc - 1) / nzc);
     g.blocks = tiles * ((a.out_e[0] + g.zlen - 1) / g.zlen);
     return g;

@@ -32,6 +32,7 @@
 #include "common.h"
 #include "gauss_grid.h"
 #include "batch.h"
+#include "tune.h"
 
 namespace harpia {
 
@@ -415,7 +416,10 @@ template <typename Tin, typename Tout, int R>
 void launch_fused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
     static const int64_t cap = resident_blocks(gauss_fused_kernel<Tin, Tout, R>, kNT);
-    const FusedGrid g = fused_grid(a, R, cap);
+    Tile t;
+    const bool tuned = tune_lookup(
+        TF_GAUSS, tune_key_volume(TF_GAUSS, R, tune_type_code<Tin>() * 8 + tune_type_code<Tout>(), a.out_e), t);
+    const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0);
     hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, taps,
                        g.zlen, g.tiles_x, g.tiles_y);
 }
@@ -424,7 +428,10 @@ template <typename Tin, int R>
 int64_t launch_dot(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
 {
     static const int64_t cap = resident_blocks(gauss_dot_kernel<Tin, R>, kNT);
-    const FusedGrid g = fused_grid(a, R, cap);
+    Tile t;
+    const bool tuned =
+        tune_lookup(TF_GAUSS_DOT, tune_key_volume(TF_GAUSS_DOT, R, tune_type_code<Tin>(), a.out_e), t);
+    const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0);
     hipLaunchKernelGGL((gauss_dot_kernel<Tin, R>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, taps, g.zlen,
                        g.tiles_x, g.tiles_y, partials);
     return g.blocks;
@@ -540,7 +547,10 @@ template <typename Tin, typename Tout, int R>
 void launch_batched(BatchDesc d, const GaussTaps &taps, hipStream_t s)
 {
     static const int64_t cap = resident_blocks(gauss_batched_kernel<Tin, Tout, R>, kNT);
-    batch_layout(d, kTX, kTY, kBatchZ);
+    Tile t;
+    const bool tuned = tune_lookup(
+        TF_GAUSS_BATCHED, tune_key_batch(TF_GAUSS_BATCHED, R, tune_type_code<Tin>() * 8 + tune_type_code<Tout>(), d), t);
+    batch_layout(d, kTX, kTY, tuned && t.tz > 0 ? t.tz : kBatchZ);
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < kBatchMaxGrid ? cap : kBatchMaxGrid);
     if (grid > 0)
         hipLaunchKernelGGL((gauss_batched_kernel<Tin, Tout, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, taps);
@@ -550,7 +560,10 @@ template <typename Tin, int R>
 int64_t launch_dot_batched(BatchDesc d, const GaussTaps &taps, hipStream_t s, float *partials)
 {
     static const int64_t cap = resident_blocks(gauss_dot_batched_kernel<Tin, R>, kNT);
-    batch_layout(d, kTX, kTY, kBatchZ);
+    Tile t;
+    const bool tuned =
+        tune_lookup(TF_GAUSS_DOT_BATCHED, tune_key_batch(TF_GAUSS_DOT_BATCHED, R, tune_type_code<Tin>(), d), t);
+    batch_layout(d, kTX, kTY, tuned && t.tz > 0 ? t.tz : kBatchZ);
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < kBatchMaxGrid ? cap : kBatchMaxGrid);
     if (grid > 0)
         hipLaunchKernelGGL((gauss_dot_batched_kernel<Tin, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, taps,

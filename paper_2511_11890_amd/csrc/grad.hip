@@ -40,6 +40,7 @@
 
 #include "common.h"
 #include "batch.h"
+#include "tune.h"
 
 namespace harpia {
 
@@ -512,15 +513,34 @@ inline int sep_zlen(const BatchDesc &d, int tx, int ty, int rz, int64_t capacity
     return zlen;
 }
 
+inline int radius_code(const int r[3]) { return r[0] * 256 + r[1] * 16 + r[2]; }
+
+// Tuned tile if recorded (and its LDS fits), else the widest fitting tile.
+template <class F>
+bool box_tile(int fam, uint64_t key, F lds_of, SepTile &tile, size_t &lds, int &zlen)
+{
+    Tile t;
+    zlen = 0;
+    if (tune_lookup(fam, key, t) && t.tx > 0 && t.ty > 0 && lds_of(t.tx, t.ty) <= 65536) {
+        tile = SepTile{t.tx, t.ty};
+        lds = lds_of(t.tx, t.ty);
+        zlen = t.tz;
+        return true;
+    }
+    return pick_sep_tile(lds_of, tile, lds);
+}
+
 template <typename T>
 bool argext_box_run(BatchDesc d, int op, const int r[3], hipStream_t s)
 {
     SepTile tile;
     size_t lds;
-    if (!pick_sep_tile([&](int tx, int ty) { return argext_box_lds(tx, ty, r[0], r[1], r[2]); }, tile, lds))
+    int zlen;
+    if (!box_tile(TF_ARGEXT_BOX, tune_key_batch(TF_ARGEXT_BOX, radius_code(r), tune_type_code<T>(), d),
+                  [&](int tx, int ty) { return argext_box_lds(tx, ty, r[0], r[1], r[2]); }, tile, lds, zlen))
         return false;
     const int64_t cap = resident_blocks(argext_box_kernel<T>, kSepThreads, lds);
-    batch_layout(d, tile.tx, tile.ty, sep_zlen(d, tile.tx, tile.ty, r[0], cap));
+    batch_layout(d, tile.tx, tile.ty, zlen > 0 ? zlen : sep_zlen(d, tile.tx, tile.ty, r[0], cap));
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap);
     if (grid > 0)
         hipLaunchKernelGGL((argext_box_kernel<T>), dim3((uint32_t)grid), dim3(kSepThreads), lds, s, d,
@@ -532,10 +552,12 @@ bool gather_box_run(BatchDesc d, const int r[3], hipStream_t s)
 {
     SepTile tile;
     size_t lds;
-    if (!pick_sep_tile([&](int tx, int ty) { return gather_box_lds(tx, ty, r[0], r[1], r[2]); }, tile, lds))
+    int zlen;
+    if (!box_tile(TF_GATHER_BOX, tune_key_batch(TF_GATHER_BOX, radius_code(r), 0, d),
+                  [&](int tx, int ty) { return gather_box_lds(tx, ty, r[0], r[1], r[2]); }, tile, lds, zlen))
         return false;
     const int64_t cap = resident_blocks(gather_box_kernel, kSepThreads, lds);
-    batch_layout(d, tile.tx, tile.ty, sep_zlen(d, tile.tx, tile.ty, r[0], cap));
+    batch_layout(d, tile.tx, tile.ty, zlen > 0 ? zlen : sep_zlen(d, tile.tx, tile.ty, r[0], cap));
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap);
     if (grid > 0)
         hipLaunchKernelGGL(gather_box_kernel, dim3((uint32_t)grid), dim3(kSepThreads), lds, s, d, r[0], r[1], r[2],

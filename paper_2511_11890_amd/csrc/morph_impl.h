@@ -34,6 +34,7 @@
 
 #include "common.h"
 #include "batch.h"
+#include "tune.h"
 
 namespace harpia {
 
@@ -87,13 +88,15 @@ struct Grid {
     int64_t blocks;
 };
 
-inline Grid make_grid(const ChunkArgs &a, int TX, int TY, int R, int64_t capacity)
+// ranges > 0: split z into that many ranges (the autotuner's choice).
+inline Grid make_grid(const ChunkArgs &a, int TX, int TY, int R, int64_t capacity, int ranges = 0)
 {
     Grid g;
     g.tiles_x = (int)((a.out_e[2] + TX - 1) / TX);
     g.tiles_y = (int)((a.out_e[1] + TY - 1) / TY);
     const int64_t tiles = (int64_t)g.tiles_x * g.tiles_y;
-    const int64_t nzc = z_ranges(a.out_e[0], tiles, capacity, R);
+    int64_t nzc = z_ranges(a.out_e[0], tiles, capacity, R);
+    if (ranges > 0) nzc = ranges < a.out_e[0] ? ranges : a.out_e[0];
     g.zlen = (int)((a.out_e[0] + nzc - 1) / nzc);
     g.blocks = tiles * ((a.out_e[0] + g.zlen - 1) / g.zlen);
     return g;
@@ -619,13 +622,19 @@ void launch_fast(const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float t
 {
     if (m.binary) {
         static const int64_t cap = resident_blocks(binary_kernel<T, SE, R, BOTH>, kNT);
-        const Grid g = make_grid(a, kBTX, kBTY, R, cap);
+        Tile t;
+        const bool tuned = tune_lookup(
+            TF_BINARY, tune_key_volume(TF_BINARY, R * 4 + SE * 2 + (BOTH ? 1 : 0), tune_type_code<T>(), a.out_e), t);
+        const Grid g = make_grid(a, kBTX, kBTY, R, cap, tuned ? t.tz : 0);
         hipLaunchKernelGGL((binary_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, o2,
                            (uint32_t)(m.op == 0 ? 1u : 0u), thr_f, (int)m.has_threshold, g.tiles_x, g.tiles_y,
                            g.zlen);
     } else {
         static const int64_t cap = resident_blocks(gray_kernel<T, SE, R, BOTH>, kNT);
-        const Grid g = make_grid(a, kGTX, kGTY, R, cap);
+        Tile t;
+        const bool tuned = tune_lookup(
+            TF_GRAY, tune_key_volume(TF_GRAY, R * 4 + SE * 2 + (BOTH ? 1 : 0), tune_type_code<T>(), a.out_e), t);
+        const Grid g = make_grid(a, kGTX, kGTY, R, cap, tuned ? t.tz : 0);
         hipLaunchKernelGGL((gray_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, o2,
                            m.op == 0 ? -1.f : 1.f, g.tiles_x, g.tiles_y, g.zlen);
     }
@@ -690,7 +699,10 @@ template <typename T, int SE, int R, bool BOTH>
 void launch_gray_batched(BatchDesc d, float sign, hipStream_t s)
 {
     static const int64_t cap = resident_blocks(gray_batched_kernel<T, SE, R, BOTH>, kNT);
-    batch_layout(d, kGTX, kGTY, 32);
+    Tile t;
+    const bool tuned = tune_lookup(
+        TF_GRAY_BATCHED, tune_key_batch(TF_GRAY_BATCHED, R * 4 + SE * 2 + (BOTH ? 1 : 0), tune_type_code<T>(), d), t);
+    batch_layout(d, kGTX, kGTY, tuned && t.tz > 0 ? t.tz : 32);
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < 8192 ? cap : 8192);
     if (grid > 0)
         hipLaunchKernelGGL((gray_batched_kernel<T, SE, R, BOTH>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, sign);
