@@ -77,6 +77,16 @@ struct Shape {
         return SE == HARPIA_SE_BOX ? R : isqrt_c(R * R - c * c - dy * dy);
     }
     static constexpr int lvl(int h) { return SE == HARPIA_SE_BOX ? 0 : h; }
+    // Widest x-run any class needs on row dy (-1: none), and whether some
+    // class takes the run of half-width h on row dy.
+    static constexpr int max_hw(int dy)
+    {
+        int m = -1;
+        for (int c = 0; c < NC; ++c)
+            if ((dy < 0 ? -dy : dy) <= rho(c) && hw(c, dy) > m) m = hw(c, dy);
+        return m;
+    }
+    static constexpr bool takes(int c, int dy, int h) { return (dy < 0 ? -dy : dy) <= rho(c) && hw(c, dy) == h; }
 };
 
 // Grid shape shared by the launchers: tiles of TX x TY columns, z ranges
@@ -105,6 +115,8 @@ inline Grid make_grid(const ChunkArgs &a, int TX, int TY, int R, int64_t capacit
 // ------------------------------------------------------------- grayscale
 
 constexpr int kGTX = 64, kGTY = 16;
+constexpr int kGC = 2;                            // output columns per thread
+constexpr int kGNT = (kGTX / kGC) * kGTY;         // threads per workgroup
 
 // Second output of the "both" kernels.
 struct Out2 {
@@ -122,14 +134,17 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
     constexpr int PWP = (PW + 3) & ~3;
     constexpr int PH = kGTY + 2 * R;
     constexpr int PSZ = PW * PH;
-    constexpr int NLD = (PSZ + kNT - 1) / kNT;
-    constexpr int NA = (kGTX / 4) * PH;  // stage A items (row, quad)
-    constexpr int NV = 4 + 2 * R;
+    constexpr int NLD = (PSZ + kGNT - 1) / kGNT;
+    constexpr int NV = kGC + 2 * R;               // patch columns one thread reads per row
     constexpr int NV4 = (NV + 3) / 4;
     constexpr int NM = BOTH ? 2 : 1;      // 0: max (dilation), 1: min
+    constexpr int BUF = PH * PWP + 4 * NV4;
 
-    __shared__ __attribute__((aligned(16))) float sP[PH * PWP + 4 * NV4];
-    __shared__ __attribute__((aligned(16))) float sH[NM][S::NL][PH * kGTX];
+    // Double-buffered patch: slice i is staged into sP[i & 1] while other
+    // threads may still read slice i - 1 from the other half, so one barrier
+    // per slice suffices.  Every thread derives the x-runs it needs straight
+    // from the patch (no intermediate LDS arrays).
+    __shared__ __attribute__((aligned(16))) float sP[2 * BUF];
 
     const int tid = threadIdx.x;
     const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
@@ -144,7 +159,7 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
     int32_t lds[NLD];
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
-        const int e = tid + i * kNT;
+        const int e = tid + i * kGNT;
         off[i] = 0;
         lds[i] = 0;
         if (e < PSZ) {
@@ -171,41 +186,41 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
         const T *base = in + (reflect_index(s0 + j, a.n[0]) - a.in_o[0]) * a.in_sz;
 #pragma unroll
         for (int i = 0; i < NLD; ++i)
-            if (i < NLD - 1 || tid + i * kNT < PSZ) pf[i] = base[off[i]];
+            if (i < NLD - 1 || tid + i * kGNT < PSZ) pf[i] = base[off[i]];
     };
 
-    const int qrow = tid / (kGTX / 4);
-    const int qcol = (tid % (kGTX / 4)) * 4;
+    const int qrow = tid / (kGTX / kGC);
+    const int qcol = (tid % (kGTX / kGC)) * kGC;
     const int64_t gy_out = y0 + qrow;
     const int64_t gx_out = x0 + qcol;
-    const int nvalid = (gy_out < yend) ? (int)min((int64_t)4, xend - gx_out) : 0;
+    const int nvalid = (gy_out < yend) ? (int)min((int64_t)kGC, xend - gx_out) : 0;
     T *outp = static_cast<T *>(a.out) + (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
     T *outp2 = BOTH ? static_cast<T *>(o2.ptr) + (gy_out - ybeg) * o2.sy + (gx_out - xbeg) : nullptr;
 
-    float acc[NM][P][4];
+    float acc[NM][P][kGC];
 #pragma unroll
     for (int m = 0; m < NM; ++m)
 #pragma unroll
         for (int j = 0; j < P; ++j)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[m][j][c] = 0.f;
+            for (int c = 0; c < kGC; ++c) acc[m][j][c] = 0.f;
 
     fetch(0);
 
-    // Step i (0 .. nsteps): store the output completed by step i - 1; if
-    // i < nsteps, filter slice i.  Stores follow the next slice's fetch so
-    // that the next staging waits only for work issued a step earlier.
+    // Step i (0 .. nsteps): stage slice i and fetch slice i + 1, store the
+    // output completed by step i - 1 (after the fetch, so that the next
+    // staging waits only for work issued a step earlier), then filter slice i.
     for (int base = 0; base <= nsteps; base += P) {
         static_for<P>([&](auto U) {
             constexpr int u = decltype(U)::value;
             const int i = base + u;
             if (i > nsteps) return;
+            float *buf = sP + (i & 1) * BUF;
             if (i < nsteps) {
-                // 1. stage (with the sign flip of a single erosion), fetch the next
 #pragma unroll
                 for (int k = 0; k < NLD; ++k)
-                    if (k < NLD - 1 || tid + k * kNT < PSZ)
-                        sP[lds[k]] = BOTH ? to_f32(pf[k]) : sign * to_f32(pf[k]);
+                    if (k < NLD - 1 || tid + k * kGNT < PSZ)
+                        buf[lds[k]] = BOTH ? to_f32(pf[k]) : sign * to_f32(pf[k]);
                 fetch(i + 1);
             }
             if (i >= 1 && i - 1 >= 2 * R && nvalid > 0) {
@@ -214,97 +229,89 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
                 if constexpr (BOTH) {
                     // out = erosion (min), out2 = dilation (max)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < kGC; ++q)
                         if (q < nvalid) {
                             outp[zl * a.out_sz + q] = from_f32<T>(acc[1][sl][q]);
                             outp2[zl * o2.sz + q] = from_f32<T>(acc[0][sl][q]);
                         }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < kGC; ++q)
                         if (q < nvalid) outp[zl * a.out_sz + q] = from_f32<T>(sign * acc[0][sl][q]);
                 }
             }
             if (i >= nsteps) return;
             lds_barrier();
 
-            // 2. stage A: x-run extrema of every level on all patch rows
+            // In-plane disc of every z-class (kGC columns): rows dy = -R .. R,
+            // each row's x-runs of the half-widths its classes take.
+            float disc[NM][S::NC][kGC];
+            static_for<P>([&](auto DY) {
+                constexpr int dy = decltype(DY)::value - R;
+                constexpr int hmax = S::max_hw(dy);
+                if constexpr (hmax >= 0) {
+                    float v[NV4 * 4];
+                    const float *prow = &buf[(qrow + R + dy) * PWP + qcol];
+                    if constexpr (kGC % 4 == 0) {
+                        const float4 *p4 = reinterpret_cast<const float4 *>(prow);
 #pragma unroll
-            for (int itk = 0; itk < (NA + kNT - 1) / kNT; ++itk) {
-                const int it = tid + itk * kNT;
-                if (itk == (NA + kNT - 1) / kNT - 1 && it >= NA) continue;
-                const int row = it / (kGTX / 4);
-                const int c0 = (it % (kGTX / 4)) * 4;
-                float v[NV4 * 4];
-                const float4 *p4 = reinterpret_cast<const float4 *>(&sP[row * PWP + c0]);
-#pragma unroll
-                for (int j = 0; j < NV4; ++j) {
-                    const float4 t4 = p4[j];
-                    v[4 * j] = t4.x;
-                    v[4 * j + 1] = t4.y;
-                    v[4 * j + 2] = t4.z;
-                    v[4 * j + 3] = t4.w;
-                }
-#pragma unroll
-                for (int m = 0; m < NM; ++m) {
-                    float run[4], res[S::NL][4];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) run[c] = v[c + R];
-                    static_for<R + 1>([&](auto H) {
-                        constexpr int h = decltype(H)::value;
-                        if constexpr (h > 0) {
-#pragma unroll
-                            for (int c = 0; c < 4; ++c)
-                                run[c] = (m == 0) ? fmaxf(run[c], fmaxf(v[c + R - h], v[c + R + h]))
-                                                  : fminf(run[c], fminf(v[c + R - h], v[c + R + h]));
+                        for (int j = 0; j < NV4; ++j) {
+                            const float4 t4 = p4[j];
+                            v[4 * j] = t4.x;
+                            v[4 * j + 1] = t4.y;
+                            v[4 * j + 2] = t4.z;
+                            v[4 * j + 3] = t4.w;
                         }
-                        if constexpr (SE != HARPIA_SE_BOX || h == R) {
+                    } else {
+                        const float2 *p2 = reinterpret_cast<const float2 *>(prow);
 #pragma unroll
-                            for (int c = 0; c < 4; ++c) res[S::lvl(h)][c] = run[c];
+                        for (int j = 0; j < 2 * NV4; ++j) {
+                            const float2 t2 = p2[j];
+                            v[2 * j] = t2.x;
+                            v[2 * j + 1] = t2.y;
                         }
-                    });
+                    }
 #pragma unroll
-                    for (int l = 0; l < S::NL; ++l)
-                        *reinterpret_cast<float4 *>(&sH[m][l][row * kGTX + c0]) =
-                            make_float4(res[l][0], res[l][1], res[l][2], res[l][3]);
+                    for (int m = 0; m < NM; ++m) {
+                        float run[kGC];
+#pragma unroll
+                        for (int q = 0; q < kGC; ++q) run[q] = v[q + R];
+                        static_for<hmax + 1>([&](auto H) {
+                            constexpr int h = decltype(H)::value;
+                            if constexpr (h > 0) {
+#pragma unroll
+                                for (int q = 0; q < kGC; ++q)
+                                    run[q] = (m == 0) ? fmaxf(run[q], fmaxf(v[q + R - h], v[q + R + h]))
+                                                      : fminf(run[q], fminf(v[q + R - h], v[q + R + h]));
+                            }
+                            static_for<S::NC>([&](auto C) {
+                                constexpr int c = decltype(C)::value;
+                                if constexpr (S::takes(c, dy, h)) {
+                                    constexpr bool first = (dy == -S::rho(c));
+#pragma unroll
+                                    for (int q = 0; q < kGC; ++q)
+                                        disc[m][c][q] = first ? run[q]
+                                                              : ((m == 0) ? fmaxf(disc[m][c][q], run[q])
+                                                                          : fminf(disc[m][c][q], run[q]));
+                                }
+                            });
+                        });
+                    }
                 }
-            }
-            lds_barrier();
-
-            // 3. stage B: in-plane disc of each z-class (4 columns), fed
-            // straight into the z ring slots of the offsets of that class
-            // (each slot takes one contribution per slice, so the order of
-            // the classes does not matter; slot (u + R) takes its first).
+            });
+            // z ring: slice i feeds the outputs i + d (offset -d) of each class;
+            // every slot takes one contribution per slice, slot (u + R) its first
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
-                static_for<S::NC>([&](auto C) {
-                    constexpr int c = decltype(C)::value;
-                    constexpr int rh = S::rho(c);
-                    float dv[4];
-                    static_for<2 * rh + 1>([&](auto DY) {
-                        constexpr int dy = decltype(DY)::value - rh;
-                        constexpr int l = S::lvl(S::hw(c, dy));
-                        const float4 t4 =
-                            *reinterpret_cast<const float4 *>(&sH[m][l][(qrow + R + dy) * kGTX + qcol]);
-                        const float tv[4] = {t4.x, t4.y, t4.z, t4.w};
+                static_for<P>([&](auto DD) {
+                    constexpr int d = decltype(DD)::value - R;
+                    constexpr int c = S::cls(d);
+                    constexpr int sl = (u + d + 2 * P) % P;
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            if constexpr (dy == -rh) dv[q] = tv[q];
-                            else dv[q] = (m == 0) ? fmaxf(dv[q], tv[q]) : fminf(dv[q], tv[q]);
-                        }
-                    });
-                    // 4. z ring: offsets d with class c
-                    static_for<P>([&](auto DD) {
-                        constexpr int d = decltype(DD)::value - R;
-                        if constexpr (S::cls(d) == c) {
-                            constexpr int sl = (u + d + 2 * P) % P;
-#pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                acc[m][sl][q] = (d == R) ? dv[q]
-                                                         : ((m == 0) ? fmaxf(acc[m][sl][q], dv[q])
-                                                                     : fminf(acc[m][sl][q], dv[q]));
-                        }
-                    });
+                    for (int q = 0; q < kGC; ++q)
+                        acc[m][sl][q] = (d == R) ? disc[m][c][q]
+                                                 : ((m == 0) ? fmaxf(acc[m][sl][q], disc[m][c][q])
+                                                             : fminf(acc[m][sl][q], disc[m][c][q]));
                 });
             }
         });
@@ -312,7 +319,7 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
 }
 
 template <typename T, int SE, int R, bool BOTH>
-__global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float sign, int tiles_x, int tiles_y,
+__global__ __launch_bounds__(kGNT) void gray_kernel(ChunkArgs a, Out2 o2, float sign, int tiles_x, int tiles_y,
                                                    int zlen)
 {
     const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -325,7 +332,7 @@ __global__ __launch_bounds__(kNT) void gray_kernel(ChunkArgs a, Out2 o2, float s
 // Persistent batched grayscale morphology (in -> out, aux -> second output
 // of a "both" step; the same element for every crop).
 template <typename T, int SE, int R, bool BOTH>
-__global__ __launch_bounds__(kNT) void gray_batched_kernel(BatchDesc d, float sign)
+__global__ __launch_bounds__(kGNT) void gray_batched_kernel(BatchDesc d, float sign)
 {
     const int total = d.prefix[d.n_crops];
     for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
@@ -630,12 +637,12 @@ void launch_fast(const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float t
                            (uint32_t)(m.op == 0 ? 1u : 0u), thr_f, (int)m.has_threshold, g.tiles_x, g.tiles_y,
                            g.zlen);
     } else {
-        static const int64_t cap = resident_blocks(gray_kernel<T, SE, R, BOTH>, kNT);
+        static const int64_t cap = resident_blocks(gray_kernel<T, SE, R, BOTH>, kGNT);
         Tile t;
         const bool tuned = tune_lookup(
             TF_GRAY, tune_key_volume(TF_GRAY, R * 4 + SE * 2 + (BOTH ? 1 : 0), tune_type_code<T>(), a.out_e), t);
         const Grid g = make_grid(a, kGTX, kGTY, R, cap, tuned ? t.tz : 0);
-        hipLaunchKernelGGL((gray_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, o2,
+        hipLaunchKernelGGL((gray_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kGNT), 0, s, a, o2,
                            m.op == 0 ? -1.f : 1.f, g.tiles_x, g.tiles_y, g.zlen);
     }
 }
@@ -698,14 +705,14 @@ namespace morph_detail {
 template <typename T, int SE, int R, bool BOTH>
 void launch_gray_batched(BatchDesc d, float sign, hipStream_t s)
 {
-    static const int64_t cap = resident_blocks(gray_batched_kernel<T, SE, R, BOTH>, kNT);
+    static const int64_t cap = resident_blocks(gray_batched_kernel<T, SE, R, BOTH>, kGNT);
     Tile t;
     const bool tuned = tune_lookup(
         TF_GRAY_BATCHED, tune_key_batch(TF_GRAY_BATCHED, R * 4 + SE * 2 + (BOTH ? 1 : 0), tune_type_code<T>(), d), t);
     batch_layout(d, kGTX, kGTY, tuned && t.tz > 0 ? t.tz : 32);
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < 8192 ? cap : 8192);
     if (grid > 0)
-        hipLaunchKernelGGL((gray_batched_kernel<T, SE, R, BOTH>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, sign);
+        hipLaunchKernelGGL((gray_batched_kernel<T, SE, R, BOTH>), dim3((uint32_t)grid), dim3(kGNT), 0, s, d, sign);
 }
 
 template <typename T, int SE, bool BOTH>
