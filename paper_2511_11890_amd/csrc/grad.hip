@@ -286,12 +286,24 @@ __host__ __device__ inline size_t gather_box_lds(int tx, int ty, int rz, int ry,
     return w * hy * sx * 6 + ty * sx * 4;
 }
 
+// Slice positions one thread stages per step (the halo'd column of a tile
+// holds at most kSepThreads * kSepPF voxels; tiles are picked to fit).
+constexpr int kSepPF = 8;
+
+// Both separable kernels take the radii and the column tile either as
+// template constants (CR: isotropic radius, CTX x CTY: tile; the common
+// case, so that index arithmetic and the offset loops fold and unroll) or,
+// with -1, as run-time arguments.
+
 // Work items: (crop, TX x TY column, z range of zlen outputs).  in = volume,
-// aux = code volume (written).
-template <typename T>
-__global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, int erode, int rz, int ry, int rx,
-                                                                 int TX, int TY)
+// aux = code volume (written).  The next slice's values are loaded into
+// registers while the current one is filtered.
+template <typename T, int CR, int CTX, int CTY>
+__global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, int erode, int rz_, int ry_, int rx_,
+                                                                 int tx_, int ty_)
 {
+    const int rz = CR >= 0 ? CR : rz_, ry = CR >= 0 ? CR : ry_, rx = CR >= 0 ? CR : rx_;
+    const int TX = CTX > 0 ? CTX : tx_, TY = CTY > 0 ? CTY : ty_;
     extern __shared__ float lds[];
     const int SX = TX + 2 * rx, HY = TY + 2 * ry, W = 2 * rz + 1, P = TY * TX;
     float *sv = lds;
@@ -308,24 +320,45 @@ __global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, in
         const T *in = static_cast<const T *>(k.in);
         uint16_t *code = static_cast<uint16_t *>(const_cast<void *>(k.aux));
         const int nz = k.n[0], ny = k.n[1], nx = k.n[2];
+        const int64_t plane = (int64_t)ny * nx;
         const int x0 = bx * TX, y0 = by * TY;
         const int z_lo = bz * k.zlen, z_hi = min(nz, z_lo + k.zlen);
+        // in-plane offsets of this thread's staged positions (clamped into
+        // the volume; clamped positions are never picked)
+        int32_t off[kSepPF];
+#pragma unroll
+        for (int j = 0; j < kSepPF; ++j) {
+            const int e = tid + j * kSepThreads;
+            const int ly = e / SX, lx = e - ly * SX;
+            const int gy = min(max(y0 - ry + ly, 0), ny - 1), gx = min(max(x0 - rx + lx, 0), nx - 1);
+            off[j] = gy * nx + gx;
+        }
+        T pf[kSepPF];
+        auto fetch = [&](int t) __attribute__((always_inline)) {
+            t = min(max(t, 0), nz - 1);
+            const T *base = in + (int64_t)t * plane;
+#pragma unroll
+            for (int j = 0; j < kSepPF; ++j)
+                if (tid + j * kSepThreads < HY * SX) pf[j] = base[off[j]];
+        };
         const int t0 = z_lo - rz;
+        fetch(t0);
         int slot = ((t0 % W) + W) % W;  // ring slot of slice t
         for (int t = t0; t < z_hi + rz; ++t) {
             const bool has_in = t >= 0 && t < nz;
             if (has_in) {
-                // stage slice t (clamped positions are never picked)
-                for (int e = tid; e < HY * SX; e += kSepThreads) {
-                    const int ly = e / SX, lx = e - ly * SX;
-                    const int gy = min(max(y0 - ry + ly, 0), ny - 1), gx = min(max(x0 - rx + lx, 0), nx - 1);
-                    const float v = to_f32(in[((int64_t)t * ny + gy) * nx + gx]);
-                    sv[e] = erode ? -v : v;
-                }
+#pragma unroll
+                for (int j = 0; j < kSepPF; ++j)
+                    if (tid + j * kSepThreads < HY * SX) {
+                        const float v = to_f32(pf[j]);
+                        sv[tid + j * kSepThreads] = erode ? -v : v;
+                    }
             }
+            fetch(t + 1);
             lds_barrier();
             if (has_in) {
                 // row stage at every row of the halo'd column
+#pragma unroll
                 for (int e = tid; e < HY * TX; e += kSepThreads) {
                     const int ly = e / TX, x = e - ly * TX, gx = x0 + x, gy = y0 - ry + ly;
                     if (gx >= nx || gy < 0 || gy >= ny) continue;
@@ -333,9 +366,10 @@ __global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, in
                     const float *row = sv + ly * SX + x + rx;
                     float best = row[lo];
                     int bi = lo;
-                    for (int dx = lo + 1; dx <= hi; ++dx) {
+#pragma unroll
+                    for (int dx = -rx + 1; dx <= rx; ++dx) {
                         const float v = row[dx];
-                        if (v > best) {
+                        if (dx > lo && dx <= hi && v > best) {
                             best = v;
                             bi = dx;
                         }
@@ -347,6 +381,7 @@ __global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, in
             lds_barrier();
             if (has_in) {
                 // plane stage; each thread keeps its own positions of the ring
+#pragma unroll
                 for (int e = tid; e < P; e += kSepThreads) {
                     const int y = e / TX, x = e - y * TX, gy = y0 + y;
                     if (gy >= ny || x0 + x >= nx) continue;
@@ -354,9 +389,10 @@ __global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, in
                     const float *col = rv + (y + ry) * TX + x;
                     float best = col[lo * TX];
                     int bi = lo;
-                    for (int dy = lo + 1; dy <= hi; ++dy) {
+#pragma unroll
+                    for (int dy = -ry + 1; dy <= ry; ++dy) {
                         const float v = col[dy * TX];
-                        if (v > best) {
+                        if (dy > lo && dy <= hi && v > best) {
                             best = v;
                             bi = dy;
                         }
@@ -371,21 +407,22 @@ __global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, in
                 // ring positions: no barrier needed)
                 const int so = wrap_slot(slot - rz, W);
                 const int lo = max(-rz, -zo), hi = min(rz, nz - 1 - zo);
+#pragma unroll
                 for (int e = tid; e < P; e += kSepThreads) {
                     const int y = e / TX, x = e - y * TX, gy = y0 + y, gx = x0 + x;
                     if (gy >= ny || gx >= nx) continue;
-                    int sz = wrap_slot(so + lo, W);
-                    float best = pv[sz * P + e];
+                    const int s_lo = wrap_slot(so + lo, W);
+                    float best = pv[s_lo * P + e];
                     int bi = lo;
-                    for (int dz = lo + 1; dz <= hi; ++dz) {
-                        sz = sz + 1 == W ? 0 : sz + 1;
-                        const float v = pv[sz * P + e];
-                        if (v > best) {
+#pragma unroll
+                    for (int dz = -rz + 1; dz <= rz; ++dz) {
+                        const float v = pv[wrap_slot(so + dz, W) * P + e];
+                        if (dz > lo && dz <= hi && v > best) {
                             best = v;
                             bi = dz;
                         }
                     }
-                    code[((int64_t)zo * ny + gy) * nx + gx] = (uint16_t)(pc[so * P + e] | (bi + rz) << 10);
+                    code[(int64_t)zo * plane + (int64_t)gy * nx + gx] = (uint16_t)(pc[so * P + e] | (bi + rz) << 10);
                 }
             }
             slot = slot + 1 == W ? 0 : slot + 1;
@@ -395,9 +432,14 @@ __global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, in
 }
 
 // Work items as in argext_box.  in = upstream gradient g, aux = codes,
-// out = grad_in.
-__global__ __launch_bounds__(kSepThreads) void gather_box_kernel(BatchDesc d, int rz, int ry, int rx, int TX, int TY)
+// out = grad_in.  The next slice's g and codes are loaded into registers
+// while the current one is pushed and routed.
+template <int CR, int CTX, int CTY>
+__global__ __launch_bounds__(kSepThreads) void gather_box_kernel(BatchDesc d, int rz_, int ry_, int rx_, int tx_,
+                                                                 int ty_)
 {
+    const int rz = CR >= 0 ? CR : rz_, ry = CR >= 0 ? CR : ry_, rx = CR >= 0 ? CR : rx_;
+    const int TX = CTX > 0 ? CTX : tx_, TY = CTY > 0 ? CTY : ty_;
     extern __shared__ float lds[];
     const int SX = TX + 2 * rx, HY = TY + 2 * ry, W = 2 * rz + 1, H = HY * SX;
     float *acc = lds;
@@ -413,28 +455,53 @@ __global__ __launch_bounds__(kSepThreads) void gather_box_kernel(BatchDesc d, in
         const uint16_t *code = static_cast<const uint16_t *>(k.aux);
         float *gin = static_cast<float *>(k.out);
         const int nz = k.n[0], ny = k.n[1], nx = k.n[2];
+        const int64_t plane = (int64_t)ny * nx;
         const int x0 = bx * TX, y0 = by * TY;
         const int z_lo = bz * k.zlen, z_hi = min(nz, z_lo + k.zlen);
+        // in-plane offsets of this thread's halo positions; -1 outside the
+        // volume (no push, invalid code)
+        int32_t off[kSepPF];
+#pragma unroll
+        for (int j = 0; j < kSepPF; ++j) {
+            const int e = tid + j * kSepThreads;
+            const int ly = e / SX, lx = e - ly * SX, gy = y0 - ry + ly, gx = x0 - rx + lx;
+            off[j] = (e < H && gy >= 0 && gy < ny && gx >= 0 && gx < nx) ? gy * nx + gx : -1;
+        }
+        float pg[kSepPF];
+        uint16_t pcd[kSepPF];
+        auto fetch = [&](int t) __attribute__((always_inline)) {
+            t = min(max(t, 0), nz - 1);
+            const int64_t base = (int64_t)t * plane;
+#pragma unroll
+            for (int j = 0; j < kSepPF; ++j)
+                if (off[j] >= 0) {
+                    pg[j] = g[base + off[j]];
+                    pcd[j] = code[base + off[j]];
+                }
+        };
         // the accumulator positions a thread clears are the ones it pushes to
         for (int e = tid; e < H; e += kSepThreads)
             for (int j = 0; j < W; ++j) acc[j * H + e] = 0.f;
         const int t0 = z_lo - rz;
+        fetch(t0);
         int slot = ((t0 % W) + W) % W;
         for (int t = t0; t < z_hi + rz; ++t) {
             if (t >= 0 && t < nz) {
                 // push slice t: G1[p + zsel(p)] += g[p] for outputs in range
-                for (int e = tid; e < H; e += kSepThreads) {
-                    const int ly = e / SX, lx = e - ly * SX, gy = y0 - ry + ly, gx = x0 - rx + lx;
+#pragma unroll
+                for (int j = 0; j < kSepPF; ++j) {
+                    const int e = tid + j * kSepThreads;
+                    if (e >= H) continue;
                     uint32_t cv = 0xffffu;
-                    if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
-                        const int64_t idx = ((int64_t)t * ny + gy) * nx + gx;
-                        cv = code[idx];
+                    if (off[j] >= 0) {
+                        cv = pcd[j];
                         const int dz = (int)(cv >> 10) - rz, q = t + dz;
-                        if (q >= z_lo && q < z_hi) acc[wrap_slot(slot + dz, W) * H + e] += g[idx];
+                        if (q >= z_lo && q < z_hi) acc[wrap_slot(slot + dz, W) * H + e] += pg[j];
                     }
                     cr[slot * H + e] = (uint16_t)cv;
                 }
             }
+            fetch(t + 1);
             lds_barrier();
             const int qz = t - rz;
             const int sq = wrap_slot(slot - rz, W);
@@ -442,9 +509,11 @@ __global__ __launch_bounds__(kSepThreads) void gather_box_kernel(BatchDesc d, in
                 // G2 = Y^T G1 over the x-halo'd rows of the tile
                 const float *a = acc + sq * H;
                 const uint16_t *cq = cr + sq * H;
+#pragma unroll
                 for (int e = tid; e < TY * SX; e += kSepThreads) {
                     const int y = e / SX, lx = e - y * SX;
                     float sum = 0.f;
+#pragma unroll
                     for (int dy = -ry; dy <= ry; ++dy) {
                         const int q = (y + ry - dy) * SX + lx;
                         if (((cq[q] >> 5) & 31) == dy + ry) sum += a[q];
@@ -456,16 +525,19 @@ __global__ __launch_bounds__(kSepThreads) void gather_box_kernel(BatchDesc d, in
             if (qz >= z_lo) {
                 // grad_in = X^T G2, then release this slice's accumulators
                 const uint16_t *cq = cr + sq * H;
+#pragma unroll
                 for (int e = tid; e < TY * TX; e += kSepThreads) {
                     const int y = e / TX, x = e - y * TX, gy = y0 + y, gx = x0 + x;
                     if (gy >= ny || gx >= nx) continue;
                     float sum = 0.f;
+#pragma unroll
                     for (int dx = -rx; dx <= rx; ++dx) {
                         const int q = x + rx - dx;
                         if ((cq[(y + ry) * SX + q] & 31) == dx + rx) sum += g2[y * SX + q];
                     }
-                    gin[((int64_t)qz * ny + gy) * nx + gx] = sum;
+                    gin[(int64_t)qz * plane + (int64_t)gy * nx + gx] = sum;
                 }
+#pragma unroll
                 for (int e = tid; e < H; e += kSepThreads) acc[sq * H + e] = 0.f;
             }
             slot = slot + 1 == W ? 0 : slot + 1;
@@ -480,13 +552,18 @@ struct SepTile {
 
 // Largest column tile whose LDS fits 64 KiB (the kernels are written for
 // any tile; wide tiles cut the halo re-reads).
+inline bool sep_tile_fits(int tx, int ty, const int r[3])
+{
+    return (ty + 2 * r[1]) * (tx + 2 * r[2]) <= kSepThreads * kSepPF;
+}
+
 template <class F>
-bool pick_sep_tile(F lds_of, SepTile &t, size_t &lds)
+bool pick_sep_tile(F lds_of, const int r[3], SepTile &t, size_t &lds)
 {
     static const SepTile cand[] = {{64, 8}, {64, 4}, {32, 4}, {32, 2}, {16, 2}, {16, 1}};
     for (const SepTile &c : cand) {
         const size_t b = lds_of(c.tx, c.ty);
-        if (b <= 65536) {
+        if (b <= 65536 && sep_tile_fits(c.tx, c.ty, r)) {
             t = c;
             lds = b;
             return true;
@@ -517,17 +594,55 @@ inline int radius_code(const int r[3]) { return r[0] * 256 + r[1] * 16 + r[2]; }
 
 // Tuned tile if recorded (and its LDS fits), else the widest fitting tile.
 template <class F>
-bool box_tile(int fam, uint64_t key, F lds_of, SepTile &tile, size_t &lds, int &zlen)
+bool box_tile(int fam, uint64_t key, F lds_of, const int r[3], SepTile &tile, size_t &lds, int &zlen)
 {
     Tile t;
     zlen = 0;
-    if (tune_lookup(fam, key, t) && t.tx > 0 && t.ty > 0 && lds_of(t.tx, t.ty) <= 65536) {
+    if (tune_lookup(fam, key, t) && t.tx > 0 && t.ty > 0 && lds_of(t.tx, t.ty) <= 65536 &&
+        sep_tile_fits(t.tx, t.ty, r)) {
         tile = SepTile{t.tx, t.ty};
         lds = lds_of(t.tx, t.ty);
         zlen = t.tz;
         return true;
     }
-    return pick_sep_tile(lds_of, tile, lds);
+    return pick_sep_tile(lds_of, r, tile, lds);
+}
+
+// Specialised instance for isotropic radius r (1..4) on the 64 x 8 tile,
+// else the run-time kernel.
+constexpr int kSpecTX = 64, kSpecTY = 8;
+
+template <typename T>
+using ArgextFn = void (*)(BatchDesc, int, int, int, int, int, int);
+using GatherFn = void (*)(BatchDesc, int, int, int, int, int);
+
+template <typename T>
+ArgextFn<T> argext_fn(const int r[3], const SepTile &t)
+{
+    if (r[0] == r[1] && r[1] == r[2] && t.tx == kSpecTX && t.ty == kSpecTY) {
+        switch (r[0]) {
+        case 1: return argext_box_kernel<T, 1, kSpecTX, kSpecTY>;
+        case 2: return argext_box_kernel<T, 2, kSpecTX, kSpecTY>;
+        case 3: return argext_box_kernel<T, 3, kSpecTX, kSpecTY>;
+        case 4: return argext_box_kernel<T, 4, kSpecTX, kSpecTY>;
+        default: break;
+        }
+    }
+    return argext_box_kernel<T, -1, -1, -1>;
+}
+
+inline GatherFn gather_fn(const int r[3], const SepTile &t)
+{
+    if (r[0] == r[1] && r[1] == r[2] && t.tx == kSpecTX && t.ty == kSpecTY) {
+        switch (r[0]) {
+        case 1: return gather_box_kernel<1, kSpecTX, kSpecTY>;
+        case 2: return gather_box_kernel<2, kSpecTX, kSpecTY>;
+        case 3: return gather_box_kernel<3, kSpecTX, kSpecTY>;
+        case 4: return gather_box_kernel<4, kSpecTX, kSpecTY>;
+        default: break;
+        }
+    }
+    return gather_box_kernel<-1, -1, -1>;
 }
 
 template <typename T>
@@ -537,14 +652,15 @@ bool argext_box_run(BatchDesc d, int op, const int r[3], hipStream_t s)
     size_t lds;
     int zlen;
     if (!box_tile(TF_ARGEXT_BOX, tune_key_batch(TF_ARGEXT_BOX, radius_code(r), tune_type_code<T>(), d),
-                  [&](int tx, int ty) { return argext_box_lds(tx, ty, r[0], r[1], r[2]); }, tile, lds, zlen))
+                  [&](int tx, int ty) { return argext_box_lds(tx, ty, r[0], r[1], r[2]); }, r, tile, lds, zlen))
         return false;
-    const int64_t cap = resident_blocks(argext_box_kernel<T>, kSepThreads, lds);
+    const ArgextFn<T> fn = argext_fn<T>(r, tile);
+    const int64_t cap = resident_blocks(fn, kSepThreads, lds);
     batch_layout(d, tile.tx, tile.ty, zlen > 0 ? zlen : sep_zlen(d, tile.tx, tile.ty, r[0], cap));
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap);
     if (grid > 0)
-        hipLaunchKernelGGL((argext_box_kernel<T>), dim3((uint32_t)grid), dim3(kSepThreads), lds, s, d,
-                           op == HARPIA_ERODE ? 1 : 0, r[0], r[1], r[2], tile.tx, tile.ty);
+        hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kSepThreads), lds, s, d, op == HARPIA_ERODE ? 1 : 0, r[0],
+                           r[1], r[2], tile.tx, tile.ty);
     return true;
 }
 
@@ -554,14 +670,15 @@ bool gather_box_run(BatchDesc d, const int r[3], hipStream_t s)
     size_t lds;
     int zlen;
     if (!box_tile(TF_GATHER_BOX, tune_key_batch(TF_GATHER_BOX, radius_code(r), 0, d),
-                  [&](int tx, int ty) { return gather_box_lds(tx, ty, r[0], r[1], r[2]); }, tile, lds, zlen))
+                  [&](int tx, int ty) { return gather_box_lds(tx, ty, r[0], r[1], r[2]); }, r, tile, lds, zlen))
         return false;
-    const int64_t cap = resident_blocks(gather_box_kernel, kSepThreads, lds);
+    const GatherFn fn = gather_fn(r, tile);
+    const int64_t cap = resident_blocks(fn, kSepThreads, lds);
     batch_layout(d, tile.tx, tile.ty, zlen > 0 ? zlen : sep_zlen(d, tile.tx, tile.ty, r[0], cap));
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap);
     if (grid > 0)
-        hipLaunchKernelGGL(gather_box_kernel, dim3((uint32_t)grid), dim3(kSepThreads), lds, s, d, r[0], r[1], r[2],
-                           tile.tx, tile.ty);
+        hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kSepThreads), lds, s, d, r[0], r[1], r[2], tile.tx,
+                           tile.ty);
     return true;
 }
 
@@ -607,6 +724,7 @@ static bool whole_volume(const ChunkArgs &a)
 {
     for (int i = 0; i < 3; ++i)
         if (a.in_o[i] != 0 || a.out_o[i] != 0 || a.out_e[i] != a.n[i] || a.n[i] > (1 << 24)) return false;
+    if (a.n[1] * a.n[2] >= ((int64_t)1 << 31)) return false;  // in-plane offsets are 32-bit
     return a.in_sy == a.n[2] && a.out_sy == a.n[2] && a.in_sz == a.n[1] * a.n[2] && a.out_sz == a.n[1] * a.n[2];
 }
 
