@@ -166,7 +166,7 @@ def traffic_summary(fetch_root: str, write_root: str, size: int, commands) -> di
     return out
 
 
-def cpu_baseline(v_dev, sample_slices: int = 24):
+def cpu_baseline(v_dev, sample_slices: int = 160):
     """FP64 oracle on a z-slab of the phantom: Gaussian sigma 1, 2, 4
     (separable, pinned equal to the direct form) and ball-3 erosion and
     dilation (brute force).  The slab is reflected at its own faces, which

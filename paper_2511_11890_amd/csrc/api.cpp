@@ -685,16 +685,22 @@ void tune_family(int fam, hipStream_t s, int reps, Call call, harpia_tune_report
     const int n = tune_candidates(fam);
     int best = 0;
     float best_ms = 0.f, heur_ms = 0.f;
-    for (int i = 0; i < n; ++i) {
-        tune_force(fam, i);
-        run();  // warm-up
+    // each candidate: one warm-up, then the fastest of `reps` runs timed one
+    // by one (the minimum is far less noisy than a mean on a shared device)
+    auto time_one = [&]() -> float {
         check_hip(hipEventRecord(ev.a, s), "hipEventRecord");
-        for (int k = 0; k < reps; ++k) run();
+        run();
         check_hip(hipEventRecord(ev.b, s), "hipEventRecord");
         check_hip(hipEventSynchronize(ev.b), "hipEventSynchronize");
         float ms = 0.f;
         check_hip(hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
-        ms /= (float)reps;
+        return ms;
+    };
+    for (int i = 0; i < n; ++i) {
+        tune_force(fam, i);
+        run();  // warm-up
+        float ms = time_one();
+        for (int k = 1; k < reps; ++k) ms = std::min(ms, time_one());
         if (i == 0) {
             heur_ms = best_ms = ms;
         } else if (ms < best_ms && ms < 0.98f * heur_ms) {
