@@ -253,6 +253,22 @@ def threshold(v, t: float) -> np.ndarray:
     return b
 
 
+def mean3d(v, radius=1, method: str = "direct") -> np.ndarray:
+    """Mean (box) filter of the filtering suite (Section III-C): the average
+    over the (2r+1)-box per axis, reflect boundary -- the convolution with
+    uniform taps 1/(2r+1) on each axis."""
+    r = _triple(radius, int)
+    taps = [np.full(2 * ri + 1, 1.0 / (2 * ri + 1)) for ri in r]
+    return conv3d(v, taps[0], taps[1], taps[2], method=method)
+
+
+def unsharp3d(v, sigma, amount: float, truncate: float = 3.0) -> np.ndarray:
+    """Unsharp masking (Section III-C): the input plus `amount` times its
+    difference from the Gaussian-smoothed input, v + a (v - G_sigma v)."""
+    v = _f64(v)
+    return v + float(amount) * (v - gaussian3d(v, sigma, truncate, method="direct"))
+
+
 def opening3d(v, se="box", radius=1):
     """Opening = dilation of the erosion, each over the full volume."""
     return dilate3d(erode3d(v, se, radius), se, radius)

@@ -484,3 +484,57 @@ def test_composite_loss_gradient_matches_central_fd():
         assert float(np.sum(gx * d)) == pytest.approx(got, rel=1e-6, abs=1e-8)
     got_s = fd(lambda h: (x, sigma + h))
     assert gs == pytest.approx(got_s, rel=1e-6, abs=1e-8)
+
+
+# ------------------------------------------------------------ mean, unsharp
+
+@pytest.mark.parametrize("shape,r", [((9, 11, 13), 1), ((7, 6, 12), (2, 1, 3)), ((3, 4, 5), 3), ((5, 6, 7), (0, 1, 2))])
+def test_mean_equals_scipy_uniform(shape, r):
+    v = _rng(60).normal(size=shape)
+    rz, ry, rx = (r, r, r) if np.ndim(r) == 0 else r
+    want = ndi.uniform_filter(v, size=(2 * rz + 1, 2 * ry + 1, 2 * rx + 1), mode="reflect")
+    np.testing.assert_allclose(oracle.mean3d(v, r), want, rtol=0, atol=1e-12)
+
+
+def test_mean_brute_force_tiny():
+    # explicit window averages over a symmetric numpy pad (not the oracle's reflect)
+    v = _rng(61).normal(size=(4, 5, 3))
+    r = (1, 2, 1)
+    p = np.pad(v, [(r[0], r[0]), (r[1], r[1]), (r[2], r[2])], mode="symmetric")
+    want = np.empty_like(v)
+    for z, y, x in itertools.product(*[range(n) for n in v.shape]):
+        want[z, y, x] = p[z:z + 2 * r[0] + 1, y:y + 2 * r[1] + 1, x:x + 2 * r[2] + 1].mean()
+    np.testing.assert_allclose(oracle.mean3d(v, r), want, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(oracle.mean3d(v, r, method="separable"), want, rtol=0, atol=1e-13)
+
+
+def test_mean_keeps_constant_and_interior_affine():
+    np.testing.assert_allclose(oracle.mean3d(np.full((6, 7, 8), 2.5), 2), 2.5, rtol=0, atol=1e-14)
+    z, y, x = np.meshgrid(np.arange(12.0), np.arange(13.0), np.arange(14.0), indexing="ij")
+    ramp = 0.3 * z - 1.1 * y + 0.7 * x + 2.0
+    out = oracle.mean3d(ramp, 2)
+    np.testing.assert_allclose(out[2:-2, 2:-2, 2:-2], ramp[2:-2, 2:-2, 2:-2], rtol=0, atol=1e-12)
+    assert np.abs(out[0] - ramp[0]).max() > 0.1  # the reflect boundary does bend a ramp
+
+
+@pytest.mark.parametrize("sigma,amount", [(1.0, 0.5), (1.5, 1.5), ((1.0, 2.0, 0.7), 0.8)])
+def test_unsharp_equals_scipy(sigma, amount):
+    v = _rng(62).normal(size=(10, 12, 14))
+    blur = ndi.gaussian_filter(v, sigma if np.ndim(sigma) else (sigma,) * 3, mode="reflect", truncate=3.0)
+    want = v + amount * (v - blur)
+    np.testing.assert_allclose(oracle.unsharp3d(v, sigma, amount), want, rtol=0, atol=1e-12)
+
+
+def test_unsharp_invariants():
+    v = _rng(63).normal(size=(8, 9, 10))
+    np.testing.assert_allclose(oracle.unsharp3d(v, 1.2, 0.0), v, rtol=0, atol=0)
+    np.testing.assert_allclose(oracle.unsharp3d(np.full((6, 6, 6), -1.5), 1.0, 2.0), -1.5, rtol=0, atol=1e-13)
+    # a symmetric normalised stencil keeps affine functions away from the faces
+    z, y, x = np.meshgrid(np.arange(16.0), np.arange(15.0), np.arange(17.0), indexing="ij")
+    ramp = 0.5 * z + 0.25 * y - 0.75 * x
+    out = oracle.unsharp3d(ramp, 1.0, 1.3)
+    np.testing.assert_allclose(out[3:-3, 3:-3, 3:-3], ramp[3:-3, 3:-3, 3:-3], rtol=0, atol=1e-12)
+    # linear in the input
+    w = _rng(64).normal(size=v.shape)
+    np.testing.assert_allclose(oracle.unsharp3d(2 * v - w, 1.0, 0.7),
+                               2 * oracle.unsharp3d(v, 1.0, 0.7) - oracle.unsharp3d(w, 1.0, 0.7), rtol=0, atol=1e-12)
