@@ -456,12 +456,61 @@ def run_batched(args):
             "tiles": tiles}
 
 
+def run_filters(args):
+    """The next filters of the suite on the resident 1024^3 float32 phantom:
+    mean (box) filter r = 1 and 2, unsharp masking sigma 2 amount 1.  One
+    step = the three filters; value = output voxels per second."""
+    import torch
+
+    import paper_2511_11890_amd as h
+    from paper_2511_11890_amd import phantoms
+
+    dev = torch.device("cuda:0")
+    n = args.size
+    v = phantoms.porous((n, n, n), seed=0, device=dev)
+    vox = v.numel()
+    out = torch.empty_like(v)
+    tiles = tiles_load(args.tiles)
+    ops = [("mean_r1", lambda: h.mean(v, 1, out=out)), ("mean_r2", lambda: h.mean(v, 2, out=out)),
+           ("unsharp_s2_a1", lambda: h.unsharp(v, 2.0, 1.0, out=out))]
+    for _ in range(args.warmup):
+        for _, fn in ops:
+            fn()
+    torch.cuda.synchronize()
+    events = {name: [] for name, _ in ops}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for name, fn in ops:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            events[name].append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_op = {}
+    for name, _ in ops:
+        ms = sum(a.elapsed_time(b) for a, b in events[name]) / len(events[name])
+        # algorithmic bytes: read once, write once (the unsharp epilogue's
+        # read of the centre voxel is a re-read)
+        per_op[name] = {"ms": round(ms, 4), "gvox_s": round(vox / ms / 1e6, 2),
+                        "hbm_frac": round(8 * vox / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    ms_step = wall * 1000 / args.steps
+    return {"metric": METRIC, "value": round(len(ops) * vox / ms_step / 1e6, 2), "unit": "GVox/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "filters: %d^3 float32 porous phantom, mean r=1,2 + unsharp sigma 2 amount 1" % n,
+                       "voxels": vox},
+            "ops": per_op, "tiles": tiles}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="resident", choices=["resident", "precision", "chunked", "batched"])
+    ap.add_argument("--workload", default="resident", choices=["resident", "precision", "chunked", "batched", "filters"])
     ap.add_argument("--size", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-ref", action="store_true",
@@ -486,9 +535,9 @@ def main():
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.size == 0:
-        args.size = 1024 if args.workload == "resident" else 2048
+        args.size = 1024 if args.workload in ("resident", "filters") else 2048
     fn = {"resident": run_resident, "precision": run_precision, "chunked": run_chunked,
-          "batched": run_batched}[args.workload]
+          "batched": run_batched, "filters": run_filters}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

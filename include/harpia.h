@@ -164,6 +164,30 @@ harpia_status harpia_gaussian3d(const void *in, harpia_dtype in_t, void *out,
                                 const double sigma[3], double truncate,
                                 harpia_border border, const harpia_exec *ex);
 
+/* Mean (box) filter (Section III-C, smoothing filters of the filtering
+ * suite): out = the average of `in` over the (2r+1)-box around each voxel,
+ * i.e. the separable convolution with taps 1 / (2 r + 1) per axis (FP64,
+ * rounded to FP32), FP32 accumulation, reflect boundary.
+ * radius[3] in [0, 64] per axis {z, y, x}; dtype pairs as for
+ * harpia_gaussian3d.  Errors: ARG, DTYPE, ALIAS, BUDGET, OOM, HIP. */
+harpia_status harpia_mean3d(const void *in, harpia_dtype in_t, void *out,
+                            harpia_dtype out_t, const int64_t shape[3],
+                            const int32_t radius[3], harpia_border border,
+                            const harpia_exec *ex);
+
+/* Unsharp masking (Section III-C, edge enhancement of the filtering suite):
+ *   out = in + amount * (in - G_sigma in) = (1 + amount) in - amount G_sigma in
+ * with G_sigma the Gaussian of harpia_gaussian3d (same taps and boundary).
+ * The Gaussian radii must be equal and in [1, 12] (the combination is an
+ * epilogue of the fused kernel), else UNSUPPORTED.  amount finite.
+ * dtype pairs as for harpia_gaussian3d.
+ * Errors: ARG, DTYPE, ALIAS, BUDGET, OOM, HIP, UNSUPPORTED. */
+harpia_status harpia_unsharp3d(const void *in, harpia_dtype in_t, void *out,
+                               harpia_dtype out_t, const int64_t shape[3],
+                               const double sigma[3], double truncate,
+                               double amount, harpia_border border,
+                               const harpia_exec *ex);
+
 /* Erosion (min over the structuring element placed at each voxel) and
  * dilation (max) (Section III-C, label editing module).
  * t: dtype of `in`.  Grayscale: out has dtype t, results are exact.

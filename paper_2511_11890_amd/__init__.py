@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import HarpiaError, harpia_plan, harpia_stats
 
-__all__ = ["gaussian", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
+__all__ = ["gaussian", "mean", "unsharp", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
            "plan", "gauss_radius", "version", "HarpiaError", "harpia_stats", "Exec",
            "gaussian_backward", "morph_backward", "GaussianFn", "MorphFn", "GaussDilateFn",
            "gaussian_batched", "morph_batched", "GaussDilateBatch", "autotune_gaussian",
@@ -171,6 +171,44 @@ def gaussian(x, sigma, truncate: float = 3.0, out=None, out_dtype=None, ex: Exec
         _lib.check(_lib.load().harpia_gaussian3d(
             _ptr(x), ic, _ptr(out), oc, _lib.i64_3(x.shape), _lib.f64_3(_triple(sigma, float)),
             float(truncate), _lib.HARPIA_BORDER_REFLECT, e))
+    return out
+
+
+def _smooth_out(x, out, out_dtype):
+    _check_volume(x)
+    ic = _dtype_code(x)
+    oc = _code(out_dtype)
+    if oc < 0:
+        oc = ic if ic in (_lib.HARPIA_F16, _lib.HARPIA_BF16) else _lib.HARPIA_F32
+    if out is None:
+        out = _empty_like(x, oc)
+    else:
+        _check_volume(out)
+        oc = _dtype_code(out)
+    return ic, oc, out
+
+
+def mean(x, radius=1, out=None, out_dtype=None, ex: Exec | None = None):
+    """Mean (box) filter: average over the (2r+1)-box per axis, reflect
+    boundary; output dtypes as for gaussian()."""
+    ic, oc, out = _smooth_out(x, out, out_dtype)
+    e = _exec(x, ex)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_mean3d(_ptr(x), ic, _ptr(out), oc, _lib.i64_3(x.shape),
+                                             _lib.i32_3(_triple(radius, int)), _lib.HARPIA_BORDER_REFLECT, e))
+    return out
+
+
+def unsharp(x, sigma, amount: float = 1.0, truncate: float = 3.0, out=None, out_dtype=None,
+            ex: Exec | None = None):
+    """Unsharp masking: x + amount (x - G_sigma x); output dtypes as for
+    gaussian().  The Gaussian radii must be equal and at most 12."""
+    ic, oc, out = _smooth_out(x, out, out_dtype)
+    e = _exec(x, ex)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_unsharp3d(
+            _ptr(x), ic, _ptr(out), oc, _lib.i64_3(x.shape), _lib.f64_3(_triple(sigma, float)), float(truncate),
+            float(amount), _lib.HARPIA_BORDER_REFLECT, e))
     return out
 
 

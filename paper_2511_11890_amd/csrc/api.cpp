@@ -246,6 +246,69 @@ harpia_status harpia_gaussian3d(const void *in, harpia_dtype in_t, void *out, ha
     });
 }
 
+// Shared checks of the Gaussian-family filters (one GAUSS stage).
+static void run_gauss_family(const void *in, harpia_dtype in_t, void *out, harpia_dtype out_t,
+                             const int64_t shape[3], harpia_border border, const harpia_exec *ex, const Stage &st)
+{
+    if (!in || !out) fail(HARPIA_ERR_ARG, "in / out is NULL");
+    check_shape(shape);
+    check_exec(ex);
+    if (border != HARPIA_BORDER_REFLECT) fail(HARPIA_ERR_ARG, "only the reflect border is supported");
+    if (!valid_dtype(in_t) || !valid_dtype(out_t)) fail(HARPIA_ERR_DTYPE, "unsupported dtype");
+    if (!gauss_pair_ok(in_t, out_t))
+        fail(HARPIA_ERR_DTYPE,
+             std::string("unsupported dtype pair ") + dtype_name(in_t) + " -> " + dtype_name(out_t));
+    const int64_t nv = voxels(shape);
+    check_alias(in, nv * dtype_size(in_t), out, nv * dtype_size(out_t));
+    Job job;
+    job.in = in;
+    job.out = out;
+    job.out2 = nullptr;
+    for (int a = 0; a < 3; ++a) job.n[a] = shape[a];
+    job.stages.push_back(st);
+    job.ex = ex;
+    run_job(job);
+}
+
+harpia_status harpia_mean3d(const void *in, harpia_dtype in_t, void *out, harpia_dtype out_t,
+                            const int64_t shape[3], const int32_t radius[3], harpia_border border,
+                            const harpia_exec *ex)
+{
+    return guarded([&] {
+        if (!radius) fail(HARPIA_ERR_ARG, "radius is NULL");
+        Stage st;
+        std::memset(&st, 0, sizeof(st));
+        st.kind = Stage::GAUSS;
+        st.in_t = in_t;
+        st.out_t = out_t;
+        int r[3];
+        for (int a = 0; a < 3; ++a) {
+            if (radius[a] < 0 || radius[a] > kMaxGaussRadius)
+                fail(HARPIA_ERR_ARG, "radius must be in [0, " + std::to_string(kMaxGaussRadius) + "]");
+            r[a] = st.r[a] = radius[a];
+        }
+        make_mean_taps(r, st.taps);
+        run_gauss_family(in, in_t, out, out_t, shape, border, ex, st);
+    });
+}
+
+harpia_status harpia_unsharp3d(const void *in, harpia_dtype in_t, void *out, harpia_dtype out_t,
+                               const int64_t shape[3], const double sigma[3], double truncate, double amount,
+                               harpia_border border, const harpia_exec *ex)
+{
+    return guarded([&] {
+        if (!sigma) fail(HARPIA_ERR_ARG, "sigma is NULL");
+        if (!std::isfinite(amount)) fail(HARPIA_ERR_ARG, "amount must be finite");
+        Stage st = gauss_stage(in_t, out_t, sigma, truncate);
+        if (!(st.r[0] == st.r[1] && st.r[1] == st.r[2]) || st.r[0] < 1 || st.r[0] > kGaussFusedMaxR)
+            fail(HARPIA_ERR_UNSUPPORTED, "unsharp masking needs equal Gaussian radii in [1, " +
+                                             std::to_string(kGaussFusedMaxR) + "]");
+        st.taps.amount = (float)amount;
+        st.taps.unsharp = 1;
+        run_gauss_family(in, in_t, out, out_t, shape, border, ex, st);
+    });
+}
+
 static harpia_status morph_common(const void *in, void *out, harpia_dtype t, const int64_t shape[3],
                                   const harpia_morph_op *ops, int32_t n_ops, harpia_se se,
                                   const int32_t radius[3], double threshold, harpia_border border,

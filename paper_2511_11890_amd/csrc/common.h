@@ -203,11 +203,15 @@ constexpr int kGaussFusedMaxR = 12;  // fused z-streaming kernel: 1 <= r <= this
 struct GaussTaps {
     int r[3];                                 // radius per axis {z, y, x}
     float w[3][kMaxGaussRadius + 1];          // half taps w[a][|k|], FP32
+    float amount;                             // unsharp mask amount a (used when unsharp != 0)
+    int unsharp;                              // 1: out = (1 + a) x - a (G x); 0: out = G x
 };
 
 // Fills taps in FP64 and rounds them to FP32 (host).
 void make_gauss_taps(const double sigma[3], double truncate, GaussTaps &t);
 void make_gauss_taps_r(const double sigma[3], const int radius[3], GaussTaps &t);
+// Uniform taps 1 / (2 r + 1) per axis (the mean filter), in FP64 then FP32.
+void make_mean_taps(const int radius[3], GaussTaps &t);
 // As make_gauss_taps_r, with axis `d_axis` replaced by d w / d sigma (radius
 // held fixed): w_k (k^2 - sum_j w_j j^2) / sigma^3, in FP64.
 void make_gauss_dtaps_r(const double sigma[3], const int radius[3], int d_axis, GaussTaps &t);

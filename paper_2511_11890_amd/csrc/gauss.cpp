@@ -65,8 +65,22 @@ size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3])
     return (size_t)((iz * iy * out_e[2] + iz * out_e[1] * out_e[2]) * (int64_t)sizeof(float));
 }
 
+void make_mean_taps(const int radius[3], GaussTaps &t)
+{
+    t.amount = 0.f;
+    t.unsharp = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int r = radius[ax];
+        t.r[ax] = r;
+        const double w = 1.0 / (double)(2 * r + 1);
+        for (int k = 0; k <= kMaxGaussRadius; ++k) t.w[ax][k] = (k <= r) ? (float)w : 0.f;
+    }
+}
+
 void make_gauss_taps_r(const double sigma[3], const int radius[3], GaussTaps &t)
 {
+    t.amount = 0.f;
+    t.unsharp = 0;
     for (int ax = 0; ax < 3; ++ax) {
         const int r = radius[ax];
         t.r[ax] = r;

@@ -95,15 +95,45 @@ constexpr int lcm_int(int a, int b) { return a / gcd_int(a, b) * b; }
 // conservatively across the step's branches).
 constexpr int gauss_prefetch_depth(int) { return 1; }
 
-// Output policies of the fused tile.  put(off, nvalid, v) receives the 4
-// finished outputs of one thread at element offset `off` of the output
-// region (a.out layout); nvalid of them lie inside the region.
-template <typename Tout>
+// Output policies of the fused tile.  put(off, in_off, nvalid, v) receives
+// the 4 finished outputs of one thread at element offset `off` of the
+// output region (a.out layout) and `in_off` of the same voxels in the input
+// region; nvalid of them lie inside the region.
+//
+// StoreOut stores them; with UNSHARP (amount a) it stores (1 + a) x - a v,
+// x the input at the same voxel (read back from the input, which holds
+// every output voxel).  A template flag, so that plain smoothing compiles
+// to the same code as without the epilogue.
+template <typename Tin, typename Tout, bool UNSHARP = false>
 struct StoreOut {
     Tout *base;
-    __device__ __forceinline__ void put(int64_t off, int nvalid, const float v[4])
+    const Tin *in;
+    float amount;
+    Tin x[4];  // UNSHARP: the input at the next output's voxels, loaded a step early
+    // Issue the loads of the next output's input values (one step ahead, so
+    // their latency hides behind a step of filtering).
+    __device__ __forceinline__ void prefetch(int64_t in_off, int nvalid)
     {
-        if (nvalid > 0) store4(base + off, v, nvalid);
+        if constexpr (UNSHARP) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c < nvalid) x[c] = in[in_off + c];
+        }
+    }
+    __device__ __forceinline__ void put(int64_t off, int64_t, int nvalid, const float v[4])
+    {
+        if (nvalid <= 0) return;
+        if constexpr (UNSHARP) {
+            float u[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float xv = c < nvalid ? to_f32(x[c]) : 0.f;
+                u[c] = fmaf(1.f + amount, xv, -amount * v[c]);
+            }
+            store4(base + off, u, nvalid);
+        } else {
+            store4(base + off, v, nvalid);
+        }
     }
 };
 
@@ -113,7 +143,8 @@ struct StoreOut {
 struct DotOut {
     const float *g;
     float sum;
-    __device__ __forceinline__ void put(int64_t off, int nvalid, const float v[4])
+    __device__ __forceinline__ void prefetch(int64_t, int) {}
+    __device__ __forceinline__ void put(int64_t off, int64_t, int nvalid, const float v[4])
     {
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -213,6 +244,7 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
     const int64_t gx_out = x0 + qcol;
     const int nvalid = (gy_out < yend) ? (int)min((int64_t)4, xend - gx_out) : 0;
     const int64_t col_off = (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
+    const int64_t in_col_off = (gy_out - a.in_o[1]) * a.in_sy + (gx_out - a.in_o[2]);
 
     float acc[P][4];
 #pragma unroll
@@ -297,7 +329,14 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
             if (i >= 1 && i - 1 >= 2 * R) {
                 constexpr int sl = (u - 1 - R + 2 * P) % P;
                 const int64_t o = s0 + (i - 1) - R;
-                out.put(col_off + (o - a.out_o[0]) * a.out_sz, nvalid, acc[sl]);
+                out.put(col_off + (o - a.out_o[0]) * a.out_sz, in_col_off + (o - a.in_o[0]) * a.in_sz, nvalid,
+                        acc[sl]);
+            }
+            // the output stored at step i + 1 (o = s0 + i - R) needs its
+            // input voxels (unsharp epilogue): load them now
+            if (i - R >= R && i < nsteps) {
+                const int64_t o = s0 + i - R;
+                out.prefetch(in_col_off + (o - a.in_o[0]) * a.in_sz, nvalid);
             }
             if (i < nsteps) lds_barrier();
         });
@@ -311,13 +350,13 @@ __device__ __forceinline__ void tile_of_block(uint32_t b, int tiles_x, int tiles
     bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
 }
 
-template <typename Tin, typename Tout, int R, int D = gauss_prefetch_depth(R)>
+template <typename Tin, typename Tout, int R, bool UNSHARP = false, int D = gauss_prefetch_depth(R)>
 __global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps taps, int zlen, int tiles_x,
                                                           int tiles_y)
 {
     int bx, by, bz;
     tile_of_block(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, bx, by, bz);
-    StoreOut<Tout> out{static_cast<Tout *>(a.out)};
+    StoreOut<Tin, Tout, UNSHARP> out{static_cast<Tout *>(a.out), static_cast<const Tin *>(a.in), taps.amount};
     gauss_tile<Tin, R, D>(a, taps, zlen, bx, by, bz, out);
 }
 
@@ -360,7 +399,7 @@ __global__ __launch_bounds__(kNT) void gauss_batched_kernel(BatchDesc d, GaussTa
         int c, bx, by, bz;
         batch_item(d, w, c, bx, by, bz);
         const ChunkArgs a = crop_args(d.c[c]);
-        StoreOut<Tout> out{static_cast<Tout *>(a.out)};
+        StoreOut<Tin, Tout> out{static_cast<Tout *>(a.out), static_cast<const Tin *>(a.in), taps.amount};
         gauss_tile<Tin, R, D>(a, taps, d.c[c].zlen, bx, by, bz, out);
         lds_barrier();
     }
@@ -412,16 +451,25 @@ __global__ __launch_bounds__(256) void gauss_pass_kernel(const Tin *src, int64_t
     }
 }
 
+template <typename Tin, typename Tout, int R, bool UNSHARP>
+void launch_fused_u(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
+{
+    static const int64_t cap = resident_blocks(gauss_fused_kernel<Tin, Tout, R, UNSHARP>, kNT);
+    Tile t;
+    const int code = tune_type_code<Tin>() * 8 + tune_type_code<Tout>() + (UNSHARP ? 64 : 0);
+    const bool tuned = tune_lookup(TF_GAUSS, tune_key_volume(TF_GAUSS, R, code, a.out_e), t);
+    const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0);
+    hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R, UNSHARP>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a,
+                       taps, g.zlen, g.tiles_x, g.tiles_y);
+}
+
 template <typename Tin, typename Tout, int R>
 void launch_fused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
-    static const int64_t cap = resident_blocks(gauss_fused_kernel<Tin, Tout, R>, kNT);
-    Tile t;
-    const bool tuned = tune_lookup(
-        TF_GAUSS, tune_key_volume(TF_GAUSS, R, tune_type_code<Tin>() * 8 + tune_type_code<Tout>(), a.out_e), t);
-    const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0);
-    hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, taps,
-                       g.zlen, g.tiles_x, g.tiles_y);
+    if (taps.unsharp)
+        launch_fused_u<Tin, Tout, R, true>(a, taps, s);
+    else
+        launch_fused_u<Tin, Tout, R, false>(a, taps, s);
 }
 
 template <typename Tin, int R>
@@ -532,6 +580,7 @@ template <typename Tin, typename Tout>
 bool run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes)
 {
     if (fused_ok(taps, a)) return dispatch_fused<Tin, Tout>(taps.r[0], a, taps, s);
+    if (taps.unsharp) return false;  // the unsharp epilogue lives in the fused kernel
     const int64_t need = (int64_t)gaussian_scratch_bytes(a.out_e, taps.r);
     if (scratch == nullptr || (int64_t)scratch_bytes < need) return false;
     launch_unfused<Tin, Tout>(a, taps, s, static_cast<float *>(scratch));

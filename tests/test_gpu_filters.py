@@ -1,0 +1,139 @@
+"""GPU parity of the mean (box) filter and unsharp masking against the FP64
+oracle (Section III-C filtering suite).
+
+Mean: a positive-weight stencil, so the FP32 bound is the Gaussian's,
+|gpu - oracle| <= 1e-5 * M(|v|) with M the mean filter; 16-bit storage
+within 2u * M(|v|).
+Unsharp, out = (1 + a) v - a G v: the Gaussian's error enters scaled by |a|
+and the combination adds a few FP32 roundings of (1 + |a|) |v|, so
+|gpu - oracle| <= 1e-5 * ((1 + |a|) |v| + |a| G(|v|)); 16-bit within
+2u times the same scale."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2511_11890_amd as h
+from paper_2511_11890_amd import phantoms
+from tests.gpu_util import FP32_GAUSS_TOL, U_BF16, U_F16, assert_gauss_close, gauss_scale, to_np64
+
+pytestmark = pytest.mark.gpu
+
+# several 64 x 16 tiles with ragged tails in x and y
+SHAPE = (37, 45, 150)
+
+
+def _mean_scale(v64, r):
+    return oracle.mean3d(np.abs(v64), r, method="separable")
+
+
+def _unsharp_scale(v64, sigma, a):
+    return (1 + abs(a)) * np.abs(v64) + abs(a) * gauss_scale(v64, sigma)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 12, (1, 2, 3), (0, 1, 2)])
+def test_mean_f32(dev, r):
+    v = phantoms.porous(SHAPE, seed=90).numpy()
+    print("mean f32", SHAPE, r, flush=True)
+    got = h.mean(torch.from_numpy(v).to(dev), r)
+    torch.cuda.synchronize()
+    v64 = v.astype(np.float64)
+    want = oracle.mean3d(v64, r, method="separable")
+    assert_gauss_close(to_np64(got), want, _mean_scale(v64, r), FP32_GAUSS_TOL, "r=%s" % (r,))
+
+
+def test_mean_direct_form_and_degenerate(dev):
+    for shape, r in (((9, 20, 70), 2), ((1, 1, 200), 3), ((3, 5, 7), 4), ((1, 1, 1), 1)):
+        v = phantoms.gaussian_noise(shape, seed=91).numpy()
+        got = h.mean(torch.from_numpy(v).to(dev), r)
+        torch.cuda.synchronize()
+        v64 = v.astype(np.float64)
+        want = oracle.mean3d(v64, r, method="direct")
+        assert_gauss_close(to_np64(got), want, _mean_scale(v64, r), FP32_GAUSS_TOL, str(shape))
+
+
+@pytest.mark.parametrize("dtype,u", [(torch.bfloat16, U_BF16), (torch.float16, U_F16)])
+def test_mean_16bit(dev, dtype, u):
+    unq, v = phantoms.porous_16bit(SHAPE, dtype=dtype, seed=92)
+    got = h.mean(v.to(dev), 2)
+    assert got.dtype == dtype
+    torch.cuda.synchronize()
+    v_unq = unq.numpy().astype(np.float64)
+    want = oracle.mean3d(v_unq, 2, method="separable")
+    assert_gauss_close(to_np64(got), want, _mean_scale(v_unq, 2), 2 * u, "16-bit")
+
+
+def test_mean_u16_to_f32_and_chunked(dev):
+    v = phantoms.porous_u16(SHAPE, seed=93)
+    res = h.mean(v.to(dev), 2)
+    torch.cuda.synchronize()
+    v64 = to_np64(v)
+    assert_gauss_close(to_np64(res), oracle.mean3d(v64, 2, method="separable"), _mean_scale(v64, 2),
+                       FP32_GAUSS_TOL, "u16")
+    chunked = h.mean(v.to(dev), 2, ex=h.Exec(force_chunked=True, chunk=(8, 16, 64), budget=64 << 20))
+    host = h.mean(v.pin_memory(), 2, ex=h.Exec(budget=8 << 20))
+    torch.cuda.synchronize()
+    assert torch.equal(chunked, res)
+    assert torch.equal(host, res.cpu())
+
+
+@pytest.mark.parametrize("sigma,amount", [(1.0, 0.5), (2.0, 1.5), (1.5, -0.5), (4.0, 1.0)])
+def test_unsharp_f32(dev, sigma, amount):
+    v = phantoms.porous(SHAPE, seed=94).numpy()
+    print("unsharp f32", SHAPE, sigma, amount, flush=True)
+    got = h.unsharp(torch.from_numpy(v).to(dev), sigma, amount)
+    torch.cuda.synchronize()
+    v64 = v.astype(np.float64)
+    want = oracle.unsharp3d(v64, sigma, amount)
+    assert_gauss_close(to_np64(got), want, _unsharp_scale(v64, sigma, amount), FP32_GAUSS_TOL,
+                       "sigma=%g a=%g" % (sigma, amount))
+
+
+def test_unsharp_zero_amount_is_identity_and_degenerate(dev):
+    v = phantoms.gaussian_noise((9, 20, 70), seed=95)
+    got = h.unsharp(v.to(dev), 2.0, 0.0)
+    torch.cuda.synchronize()
+    assert torch.equal(got.cpu(), v)
+    for shape in ((1, 1, 200), (3, 5, 7), (1, 1, 1)):
+        w = phantoms.gaussian_noise(shape, seed=96).numpy()
+        got = h.unsharp(torch.from_numpy(w).to(dev), 2.0, 1.0)
+        torch.cuda.synchronize()
+        w64 = w.astype(np.float64)
+        assert_gauss_close(to_np64(got), oracle.unsharp3d(w64, 2.0, 1.0), _unsharp_scale(w64, 2.0, 1.0),
+                           FP32_GAUSS_TOL, str(shape))
+
+
+@pytest.mark.parametrize("dtype,u", [(torch.bfloat16, U_BF16), (torch.float16, U_F16)])
+def test_unsharp_16bit(dev, dtype, u):
+    unq, v = phantoms.porous_16bit(SHAPE, dtype=dtype, seed=97)
+    got = h.unsharp(v.to(dev), 1.0, 1.0)
+    assert got.dtype == dtype
+    torch.cuda.synchronize()
+    v_unq = unq.numpy().astype(np.float64)
+    want = oracle.unsharp3d(v_unq, 1.0, 1.0)
+    assert_gauss_close(to_np64(got), want, _unsharp_scale(v_unq, 1.0, 1.0), 2 * u, "16-bit")
+
+
+def test_unsharp_chunked_equals_resident(dev):
+    v = phantoms.porous_u16(SHAPE, seed=98)
+    res = h.unsharp(v.to(dev), 2.0, 0.8)
+    dev_chunked = h.unsharp(v.to(dev), 2.0, 0.8, ex=h.Exec(force_chunked=True, chunk=(8, 16, 64), budget=64 << 20))
+    host = h.unsharp(v.pin_memory(), 2.0, 0.8, ex=h.Exec(budget=8 << 20))
+    torch.cuda.synchronize()
+    assert torch.equal(dev_chunked, res)
+    assert torch.equal(host, res.cpu())
+    v64 = to_np64(v)
+    assert_gauss_close(to_np64(res), oracle.unsharp3d(v64, 2.0, 0.8), _unsharp_scale(v64, 2.0, 0.8),
+                       FP32_GAUSS_TOL, "u16")
+
+
+def test_unsharp_limits(dev):
+    v = torch.zeros((8, 9, 10), device=dev)
+    with pytest.raises(h.HarpiaError):
+        h.unsharp(v, (1.0, 2.0, 1.0), 1.0)  # unequal radii
+    with pytest.raises(h.HarpiaError):
+        h.unsharp(v, 5.0, 1.0)  # radius 15 > 12
+    with pytest.raises(h.HarpiaError):
+        h.unsharp(v, 1.0, float("inf"))
+    with pytest.raises(h.HarpiaError):
+        h.mean(v, -1)
