@@ -449,7 +449,25 @@ harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t, const 
                 dst = static_cast<double *>(dsig.p);
             }
             const Region x_reg = whole_region(x, shape);
-            for (int axis = 0; axis < 3; ++axis) {
+            GaussTaps wt3, dt3;
+            make_gauss_taps_r(sigma, r, wt3);
+            make_gauss_dtaps3(sigma, r, dt3);
+            const bool one_pass = r[0] == r[1] && r[1] == r[2] && r[0] >= 1 && r[0] <= kGaussFusedMaxR &&
+                                  shape[1] * shape[2] < ((int64_t)1 << 31);
+            if (one_pass) {
+                // all three terms from one read of x and g
+                partials.alloc((size_t)(3 * gauss_sigma3_blocks_bound(shape)) * sizeof(float));
+                float *part = static_cast<float *>(partials.p);
+                const int64_t nb = launch_gauss_sigma3(x, x_t, static_cast<const float *>(grad_out), shape, wt3, dt3,
+                                                       s, part);
+                if (nb < 0) fail(HARPIA_ERR_UNSUPPORTED, "no fused sigma-gradient kernel for these radii");
+                check_hip(hipGetLastError(), "kernel launch");
+                for (int axis = 0; axis < 3; ++axis) {
+                    launch_reduce_f64(part + axis * nb, nb, dst + axis, false, s);
+                    check_hip(hipGetLastError(), "kernel launch");
+                }
+            }
+            for (int axis = 0; axis < 3 && !one_pass; ++axis) {
                 GaussTaps dt;
                 make_gauss_dtaps_r(sigma, r, axis, dt);
                 const ChunkArgs a = make_chunk_args(x_reg, g_reg, shape);
@@ -654,22 +672,22 @@ harpia_status harpia_gaussian3d_backward_batched(const harpia_crop *crops, int32
             const size_t need = (size_t)(3 * launches * gauss_batched_max_partials()) * sizeof(float);
             if (!workspace || workspace_bytes < need) fail(HARPIA_ERR_ARG, "workspace too small");
             if (!is_device_pointer(workspace)) fail(HARPIA_ERR_ARG, "workspace must be device memory");
+            // all three terms in one pass per launch of up to 32 crops; each
+            // launch's partials are reduced into grad_sigma in launch order
+            GaussTaps wt3, dt3;
+            make_gauss_taps_r(sigma, r, wt3);
+            make_gauss_dtaps3(sigma, r, dt3);
             float *part = static_cast<float *>(workspace);
-            for (int axis = 0; axis < 3; ++axis) {
-                GaussTaps dt;
-                make_gauss_dtaps_r(sigma, r, axis, dt);
-                int64_t n = 0;
-                for (int32_t f = 0; f < n_crops; f += kMaxBatch) {
-                    const int32_t cnt = std::min<int32_t>(kMaxBatch, n_crops - f);
-                    const int64_t got =
-                        launch_gauss_dot_batched(make_desc(crops, f, cnt, 2), HARPIA_F32, dt, s, part + n);
-                    if (got < 0) fail(HARPIA_ERR_UNSUPPORTED, "no batched dot kernel");
-                    check_hip(hipGetLastError(), "kernel launch");
-                    n += got;
-                }
-                launch_reduce_f64(part, n, grad_sigma + axis, false, s);
+            for (int32_t f = 0, l = 0; f < n_crops; f += kMaxBatch, ++l) {
+                const int32_t cnt = std::min<int32_t>(kMaxBatch, n_crops - f);
+                float *pl = part + (int64_t)l * 3 * gauss_batched_max_partials();
+                const int64_t grid = launch_gauss_sigma3_batched(make_desc(crops, f, cnt, 2), wt3, dt3, s, pl);
+                if (grid < 0) fail(HARPIA_ERR_UNSUPPORTED, "no batched sigma-gradient kernel");
                 check_hip(hipGetLastError(), "kernel launch");
-                part += launches * gauss_batched_max_partials();
+                for (int axis = 0; axis < 3; ++axis) {
+                    launch_reduce_f64(pl + axis * grid, grid, grad_sigma + axis, l > 0, s);
+                    check_hip(hipGetLastError(), "kernel launch");
+                }
             }
         }
     });

@@ -80,6 +80,10 @@ bool launch_gauss_batched(const BatchDesc &d, harpia_dtype in_t, harpia_dtype ou
 int64_t launch_gauss_dot_batched(const BatchDesc &d, harpia_dtype in_t, const GaussTaps &taps, hipStream_t s,
                                  float *partials);
 int64_t gauss_batched_max_partials();
+// The three sigma-gradient terms over a batch in one pass (in = x, out =
+// upstream gradient): partials[a grid + b]; returns grid, or -1.
+int64_t launch_gauss_sigma3_batched(const BatchDesc &d, const GaussTaps &wt, const GaussTaps &dt, hipStream_t s,
+                                    float *partials);
 // Grayscale float32 erosion / dilation (isotropic radius 1..4) over a batch;
 // with both = true, out = erosion and aux = dilation.
 bool launch_morph_batched(const BatchDesc &d, harpia_dtype t, int op, int se, int r, bool both, hipStream_t s);

@@ -215,6 +215,14 @@ void make_mean_taps(const int radius[3], GaussTaps &t);
 // As make_gauss_taps_r, with axis `d_axis` replaced by d w / d sigma (radius
 // held fixed): w_k (k^2 - sum_j w_j j^2) / sigma^3, in FP64.
 void make_gauss_dtaps_r(const double sigma[3], const int radius[3], int d_axis, GaussTaps &t);
+// d w / d sigma on every axis (the D taps of the three-term sigma-gradient).
+void make_gauss_dtaps3(const double sigma[3], const int radius[3], GaussTaps &t);
+// The three sigma-gradient terms of a dense device volume in one pass
+// (x of dtype x_t, g float32; equal radii 1..12): partials[a nb + b] for
+// axis a = z, y, x; returns nb (at most gauss_sigma3_blocks_bound), or -1.
+int64_t launch_gauss_sigma3(const void *x, harpia_dtype x_t, const float *g, const int64_t n[3], const GaussTaps &wt,
+                            const GaussTaps &dt, hipStream_t s, float *partials);
+int64_t gauss_sigma3_blocks_bound(const int64_t n[3]);
 
 // Launch the Gaussian on one chunk.  Returns false if no kernel handles the
 // dtype pair / radius combination (caller reports UNSUPPORTED).

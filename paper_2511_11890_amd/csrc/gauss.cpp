@@ -39,6 +39,49 @@ template <typename Tin, typename Tout>
 bool gauss_batched_run(const BatchDesc &d, const GaussTaps &taps, hipStream_t s);
 template <typename Tin>
 int64_t gauss_dot_batched_run(const BatchDesc &d, const GaussTaps &taps, hipStream_t s, float *partials);
+template <typename Tin>
+int64_t gauss_sigma3_run(const Tin *x, const float *g, const int64_t n[3], const GaussTaps &wt, const GaussTaps &dt,
+                         hipStream_t s, float *partials);
+template <typename Tin>
+int64_t gauss_sigma3_batched_run(const BatchDesc &d, const GaussTaps &wt, const GaussTaps &dt, hipStream_t s,
+                                 float *partials);
+
+int64_t launch_gauss_sigma3(const void *x, harpia_dtype x_t, const float *g, const int64_t n[3], const GaussTaps &wt,
+                            const GaussTaps &dt, hipStream_t s, float *partials)
+{
+    if (n[1] * n[2] >= ((int64_t)1 << 31)) return -1;  // in-plane offsets are 32-bit
+    switch (x_t) {
+    case HARPIA_F32: return gauss_sigma3_run<float>(static_cast<const float *>(x), g, n, wt, dt, s, partials);
+    case HARPIA_U16: return gauss_sigma3_run<uint16_t>(static_cast<const uint16_t *>(x), g, n, wt, dt, s, partials);
+    case HARPIA_U8: return gauss_sigma3_run<uint8_t>(static_cast<const uint8_t *>(x), g, n, wt, dt, s, partials);
+    case HARPIA_F16: return gauss_sigma3_run<_Float16>(static_cast<const _Float16 *>(x), g, n, wt, dt, s, partials);
+    case HARPIA_BF16: return gauss_sigma3_run<bf16_t>(static_cast<const bf16_t *>(x), g, n, wt, dt, s, partials);
+    }
+    return -1;
+}
+
+int64_t gauss_sigma3_blocks_bound(const int64_t n[3])
+{
+    const int64_t tiles = ((n[2] + gauss_detail::kTX - 1) / gauss_detail::kTX) *
+                          ((n[1] + gauss_detail::kTY - 1) / gauss_detail::kTY);
+    return tiles * (n[0] < gauss_detail::kMaxZRanges ? n[0] : gauss_detail::kMaxZRanges);
+}
+
+int64_t launch_gauss_sigma3_batched(const BatchDesc &d, const GaussTaps &wt, const GaussTaps &dt, hipStream_t s,
+                                    float *partials)
+{
+    return gauss_sigma3_batched_run<float>(d, wt, dt, s, partials);
+}
+
+void make_gauss_dtaps3(const double sigma[3], const int radius[3], GaussTaps &t)
+{
+    make_gauss_taps_r(sigma, radius, t);
+    for (int a = 0; a < 3; ++a) {
+        GaussTaps one;
+        make_gauss_dtaps_r(sigma, radius, a, one);
+        for (int k = 0; k <= kMaxGaussRadius; ++k) t.w[a][k] = one.w[a][k];
+    }
+}
 
 // Batched kernels are built for float32 volumes (the differentiable path).
 bool launch_gauss_batched(const BatchDesc &d, harpia_dtype in_t, harpia_dtype out_t, const GaussTaps &taps,

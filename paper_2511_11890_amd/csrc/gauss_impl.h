@@ -343,6 +343,247 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
     }
 }
 
+// Sum of 256 values in a fixed order (wave butterflies, then the 4 wave
+// sums); the result is valid in thread 0.
+__device__ __forceinline__ float block_sum_256(float v)
+{
+    __shared__ float wsum[kNT / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    lds_barrier();
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    lds_barrier();
+    return (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+// All three sigma-gradient terms of one tile in one pass.  With G the
+// Gaussian and D its sigma-derivative taps, every 1D factor is a symmetric
+// matrix under the reflect boundary, so
+//   S_z = <g, D_z G_y G_x x> = sum_s (G_y G_x x)[s] (D_z g)[s],
+//   S_y = <g, G_z D_y G_x x> = sum_s (D_y G_x x)[s] (G_z g)[s],
+//   S_x = <g, G_z G_y D_x x> = sum_s (G_y D_x x)[s] (G_z g)[s],
+// sums over every voxel s.  The tile streams slices s of x through the y and
+// x passes (both tap sets; no z halo of x is needed) while a ring of 2r+1
+// slices of g (reflected in z) gives (G_z g)[s] and (D_z g)[s] in registers.
+// x and g are dense [nz][ny][nx] volumes; g is float.  Adds this thread's
+// share of S_z, S_y, S_x over slices [zo0, zo1) of the tile to sum[3].
+template <typename Tin, int R, int D>
+__device__ __forceinline__ void sigma3_tile(const Tin *x, const float *g, const int64_t n[3], const GaussTaps &wt,
+                                            const GaussTaps &dt, int64_t x0, int64_t y0, int64_t zo0, int64_t zo1,
+                                            float sum[3])
+{
+    constexpr int P = 2 * R + 1;
+    constexpr int PW = kTX + 2 * R;
+    constexpr int PH = kTY + 2 * R;
+    constexpr int PSZ = PW * PH;
+    constexpr int NLD = (PSZ + kNT - 1) / kNT;
+    constexpr int QP = (PW + 3) & ~3;
+    constexpr int NYI = PW * (kTY / kMY);
+    constexpr int NH = 4 + 2 * R;
+    constexpr int NH4 = (NH + 3) / 4;
+    constexpr int QSZ = kTY * QP + 4 * NH4;
+
+    __shared__ float sP[2 * PSZ];
+    __shared__ __attribute__((aligned(16))) float sQG[2 * QSZ];  // y pass with G taps
+    __shared__ __attribute__((aligned(16))) float sQD[2 * QSZ];  // y pass with D taps
+
+    const int tid = threadIdx.x;
+    const int64_t nz = n[0], ny = n[1], nx = n[2];
+    const int64_t sy = nx, sz = nx * ny;
+    if (zo0 >= zo1) return;
+
+    float gz[R + 1], dz[R + 1], gy[R + 1], dy[R + 1], gx[R + 1], dx[R + 1];
+#pragma unroll
+    for (int k = 0; k <= R; ++k) {
+        gz[k] = wt.w[0][k];
+        dz[k] = dt.w[0][k];
+        gy[k] = wt.w[1][k];
+        dy[k] = dt.w[1][k];
+        gx[k] = wt.w[2][k];
+        dx[k] = dt.w[2][k];
+    }
+
+    int32_t off[NLD];
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+        const int e = tid + i * kNT;
+        off[i] = 0;
+        if (e < PSZ) {
+            const int row = e / PW, col = e - (e / PW) * PW;
+            int64_t yy = y0 - R + row;
+            yy = yy > ny - 1 + R ? ny - 1 + R : yy;
+            int64_t xx = x0 - R + col;
+            xx = xx > nx - 1 + R ? nx - 1 + R : xx;
+            off[i] = (int32_t)(reflect_index(yy, ny) * sy + reflect_index(xx, nx));
+        }
+    }
+
+    const int nsteps = (int)(zo1 - zo0);  // slices of x this range filters
+    Tin pf[D][NLD];
+    auto fetch = [&](int j, Tin(&dst)[NLD]) __attribute__((always_inline)) {
+        j = j < nsteps ? j : nsteps - 1;
+        const Tin *base = x + (zo0 + j) * sz;
+#pragma unroll
+        for (int k = 0; k < NLD; ++k)
+            if (k < NLD - 1 || tid + k * kNT < PSZ) dst[k] = base[off[k]];
+    };
+    auto stage = [&](int j, const Tin(&src)[NLD]) __attribute__((always_inline)) {
+        float *dst = sP + (j & 1) * PSZ;
+#pragma unroll
+        for (int k = 0; k < NLD; ++k)
+            if (k < NLD - 1 || tid + k * kNT < PSZ) dst[tid + k * kNT] = to_f32(src[k]);
+    };
+
+    const int qrow = tid / (kTX / 4);
+    const int qcol = (tid % (kTX / 4)) * 4;
+    const int64_t y_out = y0 + qrow, x_out = x0 + qcol;
+    const int nvalid = (y_out < ny) ? (int)min((int64_t)4, nx - x_out) : 0;
+    const float *gcol = g + (nvalid > 0 ? y_out * sy + x_out : 0);
+
+    // g ring: slot (z - (zo0 - R)) mod P holds g at the reflected slice z
+    float gr[P][4];
+    auto gload = [&](int64_t z, float(&dst)[4]) __attribute__((always_inline)) {
+        const float *p = gcol + reflect_index(z, nz) * sz;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) dst[c] = c < nvalid ? p[c] : 0.f;
+    };
+    static_for<2 * R>([&](auto K) { gload(zo0 - R + decltype(K)::value, gr[decltype(K)::value]); });
+
+    static_for<D>([&](auto DD) { fetch(decltype(DD)::value, pf[decltype(DD)::value]); });
+    stage(0, pf[0]);
+    fetch(D, pf[0]);
+    lds_barrier();
+
+    // Step i: x pass and dot of slice s = zo0 + i - 1, y pass of slice
+    // zo0 + i, staging of zo0 + i + 1, g of slice zo0 + i + R into the ring.
+    constexpr int U = lcm_int(P, D);
+    for (int base = 0; base <= nsteps; base += U) {
+        static_for<U>([&](auto UU) {
+            constexpr int u = decltype(UU)::value;
+            const int i = base + u;
+            if (i > nsteps) return;
+            if (i >= 1) {
+                const float *qg = sQG + ((i - 1) & 1) * QSZ + qrow * QP + qcol;
+                const float *qd = sQD + ((i - 1) & 1) * QSZ + qrow * QP + qcol;
+                float hg[NH4 * 4], hd[NH4 * 4];
+#pragma unroll
+                for (int j = 0; j < NH4; ++j) {
+                    const float4 a4 = reinterpret_cast<const float4 *>(qg)[j];
+                    const float4 b4 = reinterpret_cast<const float4 *>(qd)[j];
+                    hg[4 * j] = a4.x, hg[4 * j + 1] = a4.y, hg[4 * j + 2] = a4.z, hg[4 * j + 3] = a4.w;
+                    hd[4 * j] = b4.x, hd[4 * j + 1] = b4.y, hd[4 * j + 2] = b4.z, hd[4 * j + 3] = b4.w;
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    // in-plane values of slice s at column c
+                    float tGG = gx[0] * hg[c + R], tGD = dx[0] * hg[c + R], tDG = gx[0] * hd[c + R];
+#pragma unroll
+                    for (int k = 1; k <= R; ++k) {
+                        const float pg = hg[c + R - k] + hg[c + R + k];
+                        tGG = fmaf(gx[k], pg, tGG);
+                        tGD = fmaf(dx[k], pg, tGD);
+                        tDG = fmaf(gx[k], hd[c + R - k] + hd[c + R + k], tDG);
+                    }
+                    // z-filtered g at slice s (ring slots of s - R .. s + R)
+                    constexpr int sc = (u - 1 + R) % P;
+                    float zg = gz[0] * gr[sc][c], zd = dz[0] * gr[sc][c];
+                    static_for<R>([&](auto KK) {
+                        constexpr int k = decltype(KK)::value + 1;
+                        constexpr int sm = (u - 1 + R - k + P) % P, sp = (u - 1 + R + k) % P;
+                        const float pr = gr[sm][c] + gr[sp][c];
+                        zg = fmaf(gz[k], pr, zg);
+                        zd = fmaf(dz[k], pr, zd);
+                    });
+                    sum[0] = fmaf(tGG, zd, sum[0]);
+                    sum[1] = fmaf(tDG, zg, sum[1]);
+                    sum[2] = fmaf(tGD, zg, sum[2]);
+                }
+            }
+            // the ring slot of slice s - R is free now: load slice zo0 + i + R
+            {
+                constexpr int sl = (u + 2 * R) % P;
+                gload(zo0 + i + R, gr[sl]);
+            }
+            if (i < nsteps) {
+                const float *p = sP + (i & 1) * PSZ;
+                float *q = sQG + (i & 1) * QSZ;
+                float *qd = sQD + (i & 1) * QSZ;
+#pragma unroll
+                for (int itk = 0; itk < (NYI + kNT - 1) / kNT; ++itk) {
+                    const int it = tid + itk * kNT;
+                    if (itk == (NYI + kNT - 1) / kNT - 1 && it >= NYI) continue;
+                    const int col = it % PW, rg = it / PW;
+                    float v[kMY + 2 * R];
+#pragma unroll
+                    for (int j = 0; j < kMY + 2 * R; ++j) v[j] = p[(rg * kMY + j) * PW + col];
+#pragma unroll
+                    for (int m = 0; m < kMY; ++m) {
+                        float sg = gy[0] * v[m + R], sd = dy[0] * v[m + R];
+#pragma unroll
+                        for (int k = 1; k <= R; ++k) {
+                            const float pr = v[m + R - k] + v[m + R + k];
+                            sg = fmaf(gy[k], pr, sg);
+                            sd = fmaf(dy[k], pr, sd);
+                        }
+                        q[(rg * kMY + m) * QP + col] = sg;
+                        qd[(rg * kMY + m) * QP + col] = sd;
+                    }
+                }
+                constexpr int slot = (u + 1) % D;
+                stage(i + 1, pf[slot]);
+                fetch(i + 1 + D, pf[slot]);
+                lds_barrier();
+            }
+        });
+    }
+}
+
+// One workgroup per (tile, z range) of a dense volume; partials[b],
+// partials[stride + b], partials[2 stride + b] get its S_z, S_y, S_x.
+template <typename Tin, int R, int D = gauss_prefetch_depth(R)>
+__global__ __launch_bounds__(kNT) void gauss_sigma3_kernel(const Tin *x, const float *g, int64_t nz, int64_t ny,
+                                                           int64_t nx, GaussTaps wt, GaussTaps dt, int zlen,
+                                                           int tiles_x, int tiles_y, float *partials, int64_t stride)
+{
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = (int)(b % (uint32_t)tiles_x), by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
+    const int bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
+    const int64_t n[3] = {nz, ny, nx};
+    float sum[3] = {0.f, 0.f, 0.f};
+    const int64_t z0 = (int64_t)bz * zlen;
+    sigma3_tile<Tin, R, D>(x, g, n, wt, dt, (int64_t)bx * kTX, (int64_t)by * kTY, z0, min(z0 + zlen, nz), sum);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float t = block_sum_256(sum[a]);
+        if (threadIdx.x == 0) partials[a * stride + b] = t;
+    }
+}
+
+// Batched: persistent over the (crop, tile, z range) items; in = x, out =
+// upstream gradient g.  One partial per workgroup and axis.
+template <typename Tin, int R, int D = gauss_prefetch_depth(R)>
+__global__ __launch_bounds__(kNT) void gauss_sigma3_batched_kernel(BatchDesc d, GaussTaps wt, GaussTaps dt,
+                                                                   float *partials, int64_t stride)
+{
+    const int total = d.prefix[d.n_crops];
+    float sum[3] = {0.f, 0.f, 0.f};
+    for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
+        int c, bx, by, bz;
+        batch_item(d, w, c, bx, by, bz);
+        const BatchCrop &k = d.c[c];
+        const int64_t n[3] = {k.n[0], k.n[1], k.n[2]};
+        const int64_t z0 = (int64_t)bz * k.zlen;
+        sigma3_tile<Tin, R, D>(static_cast<const Tin *>(k.in), static_cast<const float *>(k.out), n, wt, dt,
+                               (int64_t)bx * kTX, (int64_t)by * kTY, z0, min(z0 + (int64_t)k.zlen, n[0]), sum);
+        lds_barrier();
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float t = block_sum_256(sum[a]);
+        if (threadIdx.x == 0) partials[a * stride + blockIdx.x] = t;
+    }
+}
+
 __device__ __forceinline__ void tile_of_block(uint32_t b, int tiles_x, int tiles_y, int &bx, int &by, int &bz)
 {
     bx = (int)(b % (uint32_t)tiles_x);
@@ -360,18 +601,6 @@ __global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps
     gauss_tile<Tin, R, D>(a, taps, zlen, bx, by, bz, out);
 }
 
-// Sum of 256 values in a fixed order (wave butterflies, then the 4 wave
-// sums); the result is valid in thread 0.
-__device__ __forceinline__ float block_sum_256(float v)
-{
-    __shared__ float wsum[kNT / 64];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    lds_barrier();
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
-    lds_barrier();
-    return (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
-}
 
 // sigma-gradient term: per-block FP32 partial of sum g * (G' x); a.out is
 // the upstream gradient g (float, laid out like the output region).
@@ -678,6 +907,112 @@ bool gauss_batched_run(const BatchDesc &d, const GaussTaps &taps, hipStream_t s)
 {
     if (!(taps.r[0] == taps.r[1] && taps.r[1] == taps.r[2])) return false;
     return gauss_detail::dispatch_batched<Tin, Tout>(taps.r[0], d, taps, s);
+}
+
+namespace gauss_detail {
+
+// z ranges of the three-term sigma-gradient: no z halo of x is read, so
+// short ranges cost only the g ring's 2r-slice prologue; enough workgroups
+// to fill the device several times, at most kMaxZRanges ranges.
+inline int sigma3_zlen(int64_t nz, int64_t tiles, int64_t cap, int ranges)
+{
+    if (ranges <= 0) {
+        ranges = 1;
+        while (ranges < kMaxZRanges && tiles * ranges < 4 * cap && nz / (2 * ranges) >= 8) ranges *= 2;
+    }
+    if (ranges > kMaxZRanges) ranges = (int)kMaxZRanges;
+    if (ranges > nz) ranges = (int)nz;
+    return (int)((nz + ranges - 1) / ranges);
+}
+
+template <typename Tin, int R>
+int64_t launch_sigma3(const Tin *x, const float *g, const int64_t n[3], const GaussTaps &wt, const GaussTaps &dt,
+                      hipStream_t s, float *partials)
+{
+    static const int64_t cap = resident_blocks(gauss_sigma3_kernel<Tin, R>, kNT);
+    const int tiles_x = (int)((n[2] + kTX - 1) / kTX), tiles_y = (int)((n[1] + kTY - 1) / kTY);
+    const int64_t tiles = (int64_t)tiles_x * tiles_y;
+    Tile t;
+    const bool tuned = tune_lookup(TF_GAUSS_DOT, tune_key_volume(TF_GAUSS_DOT, R, tune_type_code<Tin>() + 32, n), t);
+    const int zlen = sigma3_zlen(n[0], tiles, cap, tuned ? t.tz : 0);
+    const int64_t blocks = tiles * ((n[0] + zlen - 1) / zlen);
+    hipLaunchKernelGGL((gauss_sigma3_kernel<Tin, R>), dim3((uint32_t)blocks), dim3(kNT), 0, s, x, g, n[0], n[1],
+                       n[2], wt, dt, zlen, tiles_x, tiles_y, partials, blocks);
+    return blocks;
+}
+
+template <typename Tin, int R>
+int64_t launch_sigma3_batched(BatchDesc d, const GaussTaps &wt, const GaussTaps &dt, hipStream_t s, float *partials)
+{
+    static const int64_t cap = resident_blocks(gauss_sigma3_batched_kernel<Tin, R>, kNT);
+    Tile t;
+    const bool tuned = tune_lookup(TF_GAUSS_DOT_BATCHED,
+                                   tune_key_batch(TF_GAUSS_DOT_BATCHED, R, tune_type_code<Tin>() + 32, d), t);
+    batch_layout(d, kTX, kTY, tuned && t.tz > 0 ? t.tz : kBatchZ);
+    const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < kBatchMaxGrid ? cap : kBatchMaxGrid);
+    if (grid > 0)
+        hipLaunchKernelGGL((gauss_sigma3_batched_kernel<Tin, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, wt, dt,
+                           partials, grid);
+    return grid;
+}
+
+}  // namespace gauss_detail
+
+// Three-term sigma-gradient partials of a dense volume (x: Tin, g: float):
+// returns the workgroup count nb (partials[a nb + b] for axis a), or -1.
+template <typename Tin>
+int64_t gauss_sigma3_run(const Tin *x, const float *g, const int64_t n[3], const GaussTaps &wt, const GaussTaps &dt,
+                         hipStream_t s, float *partials)
+{
+    if (!(wt.r[0] == wt.r[1] && wt.r[1] == wt.r[2])) return -1;
+    switch (wt.r[0]) {
+#define HARPIA_CASE(RR) \
+    case RR:            \
+        return gauss_detail::launch_sigma3<Tin, RR>(x, g, n, wt, dt, s, partials);
+        HARPIA_CASE(1)
+        HARPIA_CASE(2)
+        HARPIA_CASE(3)
+        HARPIA_CASE(4)
+        HARPIA_CASE(5)
+        HARPIA_CASE(6)
+        HARPIA_CASE(7)
+        HARPIA_CASE(8)
+        HARPIA_CASE(9)
+        HARPIA_CASE(10)
+        HARPIA_CASE(11)
+        HARPIA_CASE(12)
+#undef HARPIA_CASE
+    default:
+        return -1;
+    }
+}
+
+// Batched: per crop in = x, out = g; partials[a grid + b]; returns grid or -1.
+template <typename Tin>
+int64_t gauss_sigma3_batched_run(const BatchDesc &d, const GaussTaps &wt, const GaussTaps &dt, hipStream_t s,
+                                 float *partials)
+{
+    if (!(wt.r[0] == wt.r[1] && wt.r[1] == wt.r[2])) return -1;
+    switch (wt.r[0]) {
+#define HARPIA_CASE(RR) \
+    case RR:            \
+        return gauss_detail::launch_sigma3_batched<Tin, RR>(d, wt, dt, s, partials);
+        HARPIA_CASE(1)
+        HARPIA_CASE(2)
+        HARPIA_CASE(3)
+        HARPIA_CASE(4)
+        HARPIA_CASE(5)
+        HARPIA_CASE(6)
+        HARPIA_CASE(7)
+        HARPIA_CASE(8)
+        HARPIA_CASE(9)
+        HARPIA_CASE(10)
+        HARPIA_CASE(11)
+        HARPIA_CASE(12)
+#undef HARPIA_CASE
+    default:
+        return -1;
+    }
 }
 
 template <typename Tin>
