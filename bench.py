@@ -496,13 +496,31 @@ def run_filters(args):
         per_op[name] = {"ms": round(ms, 4), "gvox_s": round(vox / ms / 1e6, 2),
                         "hbm_frac": round(8 * vox / ms / 1e6 / HBM_PEAK_GBS, 4)}
     ms_step = wall * 1000 / args.steps
-    return {"metric": METRIC, "value": round(len(ops) * vox / ms_step / 1e6, 2), "unit": "GVox/s", "n_gpus": 1,
+    dom = max(per_op, key=lambda k: per_op[k]["ms"])
+    d = per_op[dom]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(8 * vox / d["ms"] / 1e6, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": d["hbm_frac"], "per_launch": {"bytes": 8 * vox, "ms": d["ms"]}, "traffic": None}
+    line = {"metric": METRIC, "value": round(len(ops) * vox / ms_step / 1e6, 2), "unit": "GVox/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": "filters: %d^3 float32 porous phantom, mean r=1,2 + unsharp sigma 2 amount 1" % n,
                        "voxels": vox},
-            "ops": per_op, "tiles": tiles}
+            "roofline": roof, "ops": per_op, "tiles": tiles}
+    if not args.no_cpu:
+        import oracle
+
+        sl = v[:32].double().cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.mean3d(sl, 1, method="separable")
+        oracle.mean3d(sl, 2, method="separable")
+        oracle.unsharp3d(sl, 2.0, 1.0)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": round(3 * sl.size / dt / 1e9, 6), "unit": "GVox/s",
+                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": "%dx%dx%d slab: separable FP64 mean r=1,2 + unsharp (direct FP64 Gaussian) "
+                                          "sigma 2, %.1f s" % (sl.shape + (dt,))}
+    return line
 
 
 def main():
