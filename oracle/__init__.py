@@ -269,6 +269,23 @@ def unsharp3d(v, sigma, amount: float, truncate: float = 3.0) -> np.ndarray:
     return v + float(amount) * (v - gaussian3d(v, sigma, truncate, method="direct"))
 
 
+def edge3d_axes(v, kind: str = "sobel"):
+    """The three per-axis responses of the Sobel / Prewitt operator
+    (Section III-C, edge enhancement): along axis a the central difference
+    [-1, 0, 1] (v[i+1] - v[i-1]), along the other two axes the smoothing
+    [1, 2, 1] (Sobel) or [1, 1, 1] (Prewitt); reflect boundary."""
+    sm = np.array([1.0, 2.0, 1.0]) if kind == "sobel" else np.array([1.0, 1.0, 1.0])
+    d = np.array([-1.0, 0.0, 1.0])
+    return [conv3d(v, *[d if b == a else sm for b in range(3)], method="direct") for a in range(3)]
+
+
+def edge3d(v, kind: str = "sobel") -> np.ndarray:
+    """Gradient magnitude sqrt(Gz^2 + Gy^2 + Gx^2) of the Sobel / Prewitt
+    operator (unnormalised weights)."""
+    gz, gy, gx = edge3d_axes(v, kind)
+    return np.sqrt(gz * gz + gy * gy + gx * gx)
+
+
 def opening3d(v, se="box", radius=1):
     """Opening = dilation of the erosion, each over the full volume."""
     return dilate3d(erode3d(v, se, radius), se, radius)

@@ -538,3 +538,42 @@ def test_unsharp_invariants():
     w = _rng(64).normal(size=v.shape)
     np.testing.assert_allclose(oracle.unsharp3d(2 * v - w, 1.0, 0.7),
                                2 * oracle.unsharp3d(v, 1.0, 0.7) - oracle.unsharp3d(w, 1.0, 0.7), rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------- Sobel / Prewitt
+
+@pytest.mark.parametrize("kind", ["sobel", "prewitt"])
+@pytest.mark.parametrize("shape", [(7, 9, 11), (3, 1, 5), (1, 1, 4)])
+def test_edge_equals_scipy(kind, shape):
+    v = _rng(70).normal(size=shape)
+    op = ndi.sobel if kind == "sobel" else ndi.prewitt
+    for a, got in enumerate(oracle.edge3d_axes(v, kind)):
+        np.testing.assert_allclose(got, op(v, axis=a, mode="reflect"), rtol=0, atol=1e-12)
+    want = ndi.generic_gradient_magnitude(v, op, mode="reflect")
+    np.testing.assert_allclose(oracle.edge3d(v, kind), want, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind,gain", [("sobel", 32.0), ("prewitt", 18.0)])
+def test_edge_constant_and_ramp_closed_form(kind, gain):
+    np.testing.assert_allclose(oracle.edge3d(np.full((5, 6, 7), 3.0), kind), 0.0, rtol=0, atol=1e-13)
+    # interior of an affine ramp: each axis responds 2 * slope * (sum of the
+    # two smoothing kernels' weights: 4 * 4 Sobel, 3 * 3 Prewitt)
+    z, y, x = np.meshgrid(np.arange(8.0), np.arange(9.0), np.arange(10.0), indexing="ij")
+    a, b, c = 0.5, -1.25, 2.0
+    out = oracle.edge3d(a * z + b * y + c * x, kind)
+    np.testing.assert_allclose(out[1:-1, 1:-1, 1:-1], gain * math.sqrt(a * a + b * b + c * c), rtol=1e-13)
+
+
+def test_edge_brute_force_tiny():
+    v = _rng(71).normal(size=(3, 4, 5))
+    p = np.pad(v, 1, mode="symmetric")
+    sm = np.array([1.0, 2.0, 1.0])
+    d = np.array([-1.0, 0.0, 1.0])
+    want = np.empty_like(v)
+    for z, y, x in itertools.product(*[range(n) for n in v.shape]):
+        w = p[z:z + 3, y:y + 3, x:x + 3]
+        gz = np.einsum("i,j,k,ijk->", d, sm, sm, w)
+        gy = np.einsum("i,j,k,ijk->", sm, d, sm, w)
+        gx = np.einsum("i,j,k,ijk->", sm, sm, d, w)
+        want[z, y, x] = math.sqrt(gz * gz + gy * gy + gx * gx)
+    np.testing.assert_allclose(oracle.edge3d(v, "sobel"), want, rtol=0, atol=1e-12)
