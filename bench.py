@@ -458,8 +458,9 @@ def run_batched(args):
 
 def run_filters(args):
     """The next filters of the suite on the resident 1024^3 float32 phantom:
-    mean (box) filter r = 1 and 2, unsharp masking sigma 2 amount 1.  One
-    step = the three filters; value = output voxels per second."""
+    mean (box) filter r = 1 and 2, unsharp masking sigma 2 amount 1, Sobel
+    gradient magnitude.  One step = the four filters; value = output voxels
+    per second."""
     import torch
 
     import paper_2511_11890_amd as h
@@ -472,7 +473,7 @@ def run_filters(args):
     out = torch.empty_like(v)
     tiles = tiles_load(args.tiles)
     ops = [("mean_r1", lambda: h.mean(v, 1, out=out)), ("mean_r2", lambda: h.mean(v, 2, out=out)),
-           ("unsharp_s2_a1", lambda: h.unsharp(v, 2.0, 1.0, out=out))]
+           ("unsharp_s2_a1", lambda: h.unsharp(v, 2.0, 1.0, out=out)), ("sobel", lambda: h.edge(v, "sobel", out=out))]
     for _ in range(args.warmup):
         for _, fn in ops:
             fn()
@@ -504,7 +505,8 @@ def run_filters(args):
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
-            "config": {"workload": "filters: %d^3 float32 porous phantom, mean r=1,2 + unsharp sigma 2 amount 1" % n,
+            "config": {"workload": "filters: %d^3 float32 porous phantom, mean r=1,2 + unsharp sigma 2 amount 1 + "
+                                   "Sobel magnitude" % n,
                        "voxels": vox},
             "roofline": roof, "ops": per_op, "tiles": tiles}
     if not args.no_cpu:
@@ -515,11 +517,12 @@ def run_filters(args):
         oracle.mean3d(sl, 1, method="separable")
         oracle.mean3d(sl, 2, method="separable")
         oracle.unsharp3d(sl, 2.0, 1.0)
+        oracle.edge3d(sl, "sobel")
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": round(3 * sl.size / dt / 1e9, 6), "unit": "GVox/s",
+        line["cpu_baseline"] = {"value": round(4 * sl.size / dt / 1e9, 6), "unit": "GVox/s",
                                 "cores": oracle.num_threads(), "kind": "oracle",
                                 "sample": "%dx%dx%d slab: separable FP64 mean r=1,2 + unsharp (direct FP64 Gaussian) "
-                                          "sigma 2, %.1f s" % (sl.shape + (dt,))}
+                                          "sigma 2 + direct FP64 Sobel, %.1f s" % (sl.shape + (dt,))}
     return line
 
 

@@ -188,6 +188,20 @@ harpia_status harpia_unsharp3d(const void *in, harpia_dtype in_t, void *out,
                                double amount, harpia_border border,
                                const harpia_exec *ex);
 
+/* Sobel / Prewitt edge enhancement (Section III-C, filtering suite):
+ *   G_a = central difference [-1, 0, 1] (in[i+1] - in[i-1]) along axis a,
+ *         smoothed by [1, 2, 1] (HARPIA_EDGE_SOBEL) or [1, 1, 1]
+ *         (HARPIA_EDGE_PREWITT) along the two other axes (unnormalised);
+ *   out = sqrt(G_z^2 + G_y^2 + G_x^2), reflect boundary, FP32 arithmetic.
+ * dtype pairs as for harpia_gaussian3d.
+ * Errors: ARG, DTYPE, ALIAS, BUDGET, OOM, HIP, UNSUPPORTED. */
+typedef enum { HARPIA_EDGE_SOBEL = 0, HARPIA_EDGE_PREWITT = 1 } harpia_edge;
+
+harpia_status harpia_edge3d(const void *in, harpia_dtype in_t, void *out,
+                            harpia_dtype out_t, const int64_t shape[3],
+                            harpia_edge kind, harpia_border border,
+                            const harpia_exec *ex);
+
 /* Erosion (min over the structuring element placed at each voxel) and
  * dilation (max) (Section III-C, label editing module).
  * t: dtype of `in`.  Grayscale: out has dtype t, results are exact.

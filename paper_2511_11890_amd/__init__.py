@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import HarpiaError, harpia_plan, harpia_stats
 
-__all__ = ["gaussian", "mean", "unsharp", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
+__all__ = ["gaussian", "mean", "unsharp", "edge", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
            "plan", "gauss_radius", "version", "HarpiaError", "harpia_stats", "Exec",
            "gaussian_backward", "morph_backward", "GaussianFn", "MorphFn", "GaussDilateFn",
            "gaussian_batched", "morph_batched", "GaussDilateBatch", "autotune_gaussian",
@@ -209,6 +209,17 @@ def unsharp(x, sigma, amount: float = 1.0, truncate: float = 3.0, out=None, out_
         _lib.check(_lib.load().harpia_unsharp3d(
             _ptr(x), ic, _ptr(out), oc, _lib.i64_3(x.shape), _lib.f64_3(_triple(sigma, float)), float(truncate),
             float(amount), _lib.HARPIA_BORDER_REFLECT, e))
+    return out
+
+
+def edge(x, kind: str = "sobel", out=None, out_dtype=None, ex: Exec | None = None):
+    """Sobel / Prewitt gradient magnitude (unnormalised weights, reflect
+    boundary); output dtypes as for gaussian()."""
+    ic, oc, out = _smooth_out(x, out, out_dtype)
+    e = _exec(x, ex)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_edge3d(_ptr(x), ic, _ptr(out), oc, _lib.i64_3(x.shape),
+                                             {"sobel": 0, "prewitt": 1}[kind], _lib.HARPIA_BORDER_REFLECT, e))
     return out
 
 

@@ -292,6 +292,22 @@ harpia_status harpia_mean3d(const void *in, harpia_dtype in_t, void *out, harpia
     });
 }
 
+harpia_status harpia_edge3d(const void *in, harpia_dtype in_t, void *out, harpia_dtype out_t,
+                            const int64_t shape[3], harpia_edge kind, harpia_border border, const harpia_exec *ex)
+{
+    return guarded([&] {
+        if (kind != HARPIA_EDGE_SOBEL && kind != HARPIA_EDGE_PREWITT) fail(HARPIA_ERR_ARG, "unknown edge operator");
+        Stage st;
+        std::memset(&st, 0, sizeof(st));
+        st.kind = Stage::EDGE;
+        st.in_t = in_t;
+        st.out_t = out_t;
+        for (int a = 0; a < 3; ++a) st.r[a] = 1;
+        st.edge = (int)kind;
+        run_gauss_family(in, in_t, out, out_t, shape, border, ex, st);
+    });
+}
+
 harpia_status harpia_unsharp3d(const void *in, harpia_dtype in_t, void *out, harpia_dtype out_t,
                                const int64_t shape[3], const double sigma[3], double truncate, double amount,
                                harpia_border border, const harpia_exec *ex)

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 #include <cstdlib>
 #include <string>
 
@@ -86,6 +87,19 @@ __device__ __forceinline__ void lds_barrier()
 // ------------------------------------------------------------ reflection
 
 // Half-sample symmetric reflection of i into [0, n), valid for any i.
+// Calls f(std::integral_constant<int, I>) for I = 0..N-1 with I a
+// compile-time constant, so register arrays indexed by I stay in registers.
+template <int... I, class F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, F &&f)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(std::make_integer_sequence<int, N>{}, static_cast<F &&>(f));
+}
+
 __host__ __device__ __forceinline__ int64_t reflect_index(int64_t i, int64_t n)
 {
     if (i >= 0 && i < n) return i;
@@ -229,6 +243,9 @@ int64_t gauss_sigma3_blocks_bound(const int64_t n[3]);
 bool launch_gaussian(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t,
                      const GaussTaps &taps, hipStream_t s, void *scratch,
                      size_t scratch_bytes);
+// Sobel (kind 0) / Prewitt (kind 1) gradient magnitude of one chunk (radius
+// 1 halo); dtype pairs as for the Gaussian.
+bool launch_edge(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t, int kind, hipStream_t s);
 // Scratch bytes the Gaussian needs for an output region of `out_e` voxels
 // (0 for the fused kernel).
 size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3]);

@@ -36,18 +36,6 @@
 
 namespace harpia {
 
-// Calls f(std::integral_constant<int, I>) for I = 0..N-1 with I a
-// compile-time constant, so register arrays indexed by I stay in registers.
-template <int... I, class F>
-__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, F &&f)
-{
-    (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, class F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    static_for_impl(std::make_integer_sequence<int, N>{}, static_cast<F &&>(f));
-}
 
 namespace gauss_detail {
 

@@ -38,19 +38,6 @@
 
 namespace harpia {
 
-#ifndef HARPIA_STATIC_FOR_DEFINED
-#define HARPIA_STATIC_FOR_DEFINED
-template <int... I, class F>
-__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, F &&f)
-{
-    (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, class F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    static_for_impl(std::make_integer_sequence<int, N>{}, static_cast<F &&>(f));
-}
-#endif
 
 namespace morph_detail {
 

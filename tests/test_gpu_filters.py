@@ -137,3 +137,60 @@ def test_unsharp_limits(dev):
         h.unsharp(v, 1.0, float("inf"))
     with pytest.raises(h.HarpiaError):
         h.mean(v, -1)
+
+
+# ------------------------------------------------------- Sobel / Prewitt
+# Each axis response errs by at most eps * (|taps| * |v|), so the magnitude
+# errs by at most eps * sqrt(sum_a (|taps_a| * |v|)^2).
+
+def _edge_scale(v64, kind):
+    sm = np.array([1.0, 2.0, 1.0]) if kind == "sobel" else np.ones(3)
+    d = np.array([1.0, 0.0, 1.0])
+    av = np.abs(v64)
+    s2 = 0.0
+    for a in range(3):
+        s2 = s2 + oracle.conv3d(av, *[d if b == a else sm for b in range(3)], method="separable") ** 2
+    return np.sqrt(s2)
+
+
+@pytest.mark.parametrize("kind", ["sobel", "prewitt"])
+def test_edge_f32(dev, kind):
+    v = phantoms.porous(SHAPE, seed=99).numpy()
+    print("edge f32", SHAPE, kind, flush=True)
+    got = h.edge(torch.from_numpy(v).to(dev), kind)
+    torch.cuda.synchronize()
+    v64 = v.astype(np.float64)
+    assert_gauss_close(to_np64(got), oracle.edge3d(v64, kind), _edge_scale(v64, kind), FP32_GAUSS_TOL, kind)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 200), (3, 5, 7), (1, 1, 1), (2, 70, 1), (70, 1, 2), (5, 16, 64)])
+def test_edge_degenerate_shapes(dev, shape):
+    v = phantoms.gaussian_noise(shape, seed=100).numpy()
+    got = h.edge(torch.from_numpy(v).to(dev), "sobel")
+    torch.cuda.synchronize()
+    v64 = v.astype(np.float64)
+    assert_gauss_close(to_np64(got), oracle.edge3d(v64, "sobel"), _edge_scale(v64, "sobel"), FP32_GAUSS_TOL,
+                       str(shape))
+
+
+@pytest.mark.parametrize("dtype,u", [(torch.bfloat16, U_BF16), (torch.float16, U_F16)])
+def test_edge_16bit(dev, dtype, u):
+    unq, v = phantoms.porous_16bit(SHAPE, dtype=dtype, seed=101)
+    got = h.edge(v.to(dev), "sobel")
+    assert got.dtype == dtype
+    torch.cuda.synchronize()
+    v_unq = unq.numpy().astype(np.float64)
+    assert_gauss_close(to_np64(got), oracle.edge3d(v_unq, "sobel"), _edge_scale(v_unq, "sobel"), 2 * u, "16-bit")
+
+
+def test_edge_u16_chunked_equals_resident(dev):
+    v = phantoms.porous_u16(SHAPE, seed=102)
+    res = h.edge(v.to(dev), "prewitt")
+    dev_chunked = h.edge(v.to(dev), "prewitt", ex=h.Exec(force_chunked=True, chunk=(8, 16, 64), budget=64 << 20))
+    host = h.edge(v.pin_memory(), "prewitt", ex=h.Exec(budget=8 << 20))
+    torch.cuda.synchronize()
+    assert torch.equal(dev_chunked, res)
+    assert torch.equal(host, res.cpu())
+    v64 = to_np64(v)
+    assert_gauss_close(to_np64(res), oracle.edge3d(v64, "prewitt"), _edge_scale(v64, "prewitt"), FP32_GAUSS_TOL,
+                       "u16")
