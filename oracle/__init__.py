@@ -286,6 +286,43 @@ def edge3d(v, kind: str = "sobel") -> np.ndarray:
     return np.sqrt(gz * gz + gy * gy + gx * gx)
 
 
+def gauss_deriv_taps(sigma: float, r: int, order: int) -> np.ndarray:
+    """Correlation taps c[k + r] of the order-th derivative of the Gaussian
+    smoothing along one axis: with w the normalised taps, c = w (order 0),
+    (k / s^2) w (order 1: d/dx of the smoothed signal, v[i + k] weighted by
+    c[k]), ((k^2 - s^2) / s^4) w (order 2)."""
+    w = gauss_taps(sigma, r)
+    k = np.arange(-r, r + 1, dtype=np.float64)
+    s2 = float(sigma) ** 2
+    if order == 0:
+        return w
+    if order == 1:
+        return k / s2 * w
+    if order == 2:
+        return (k * k - s2) / (s2 * s2) * w
+    raise ValueError("order must be 0, 1 or 2")
+
+
+HESSIAN_PAIRS = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))
+
+
+def hessian3d(v, sigma, truncate: float = 3.0) -> np.ndarray:
+    """Hessian of the Gaussian-smoothed volume (Section III-C texture
+    features): components zz, zy, zx, yy, yx, xx, each the separable
+    correlation with derivative taps of the orders the pair asks for;
+    reflect boundary.  Returns an array [6, nz, ny, nx]."""
+    s = _triple(sigma, float)
+    r = tuple(gauss_radius(si, truncate) for si in s)
+    out = []
+    for a, b in HESSIAN_PAIRS:
+        orders = [0, 0, 0]
+        orders[a] += 1
+        orders[b] += 1
+        taps = [gauss_deriv_taps(s[i], r[i], orders[i]) for i in range(3)]
+        out.append(conv3d(v, *taps, method="direct"))
+    return np.stack(out)
+
+
 def opening3d(v, se="box", radius=1):
     """Opening = dilation of the erosion, each over the full volume."""
     return dilate3d(erode3d(v, se, radius), se, radius)

@@ -577,3 +577,49 @@ def test_edge_brute_force_tiny():
         gx = np.einsum("i,j,k,ijk->", sm, sm, d, w)
         want[z, y, x] = math.sqrt(gz * gz + gy * gy + gx * gx)
     np.testing.assert_allclose(oracle.edge3d(v, "sobel"), want, rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------- Hessian
+
+@pytest.mark.parametrize("sigma", [1.0, 1.6, (1.0, 2.0, 0.8)])
+def test_hessian_equals_scipy(sigma):
+    v = _rng(80).normal(size=(11, 12, 13))
+    got = oracle.hessian3d(v, sigma)
+    for c, (a, b) in enumerate(oracle.HESSIAN_PAIRS):
+        order = [0, 0, 0]
+        order[a] += 1
+        order[b] += 1
+        want = ndi.gaussian_filter(v, sigma, order=order, mode="reflect", truncate=3.0)
+        np.testing.assert_allclose(got[c], want, rtol=0, atol=1e-12, err_msg=str((a, b)))
+
+
+def test_hessian_parity_under_flips():
+    # even-order components commute with a flip of an axis; components odd
+    # in that axis change sign
+    v = _rng(81).normal(size=(9, 10, 11))
+    h = oracle.hessian3d(v, 1.2)
+    for axis in range(3):
+        hf = oracle.hessian3d(np.flip(v, axis), 1.2)
+        for c, (a, b) in enumerate(oracle.HESSIAN_PAIRS):
+            sign = -1.0 if (a == axis) != (b == axis) else 1.0
+            np.testing.assert_allclose(hf[c], sign * np.flip(h[c], axis), rtol=0, atol=1e-12)
+
+
+def test_deriv_taps_moments():
+    # sampled derivative taps (M2 = sum k^2 w_k of the normalised taps):
+    # order 1 is odd with sum k c_k = M2 / s^2, order 2 is even with
+    # sum c_k = (M2 - s^2) / s^4
+    for sigma in (1.0, 2.0, 3.5):
+        r = oracle.gauss_radius(sigma)
+        k = np.arange(-r, r + 1.0)
+        w = oracle.gauss_taps(sigma, r)
+        m2 = np.sum(k * k * w)
+        c1 = oracle.gauss_deriv_taps(sigma, r, 1)
+        c2 = oracle.gauss_deriv_taps(sigma, r, 2)
+        np.testing.assert_allclose(c1, -c1[::-1], rtol=0, atol=0)
+        np.testing.assert_allclose(np.sum(k * c1), m2 / sigma ** 2, rtol=1e-14)
+        np.testing.assert_allclose(c2, c2[::-1], rtol=0, atol=0)
+        np.testing.assert_allclose(np.sum(c2), (m2 - sigma ** 2) / sigma ** 4, rtol=1e-12, atol=1e-15)
+        # truncation at 3 sigma keeps M2 within 1.5 % of s^2, so the
+        # derivative of a unit ramp is close to 1
+        assert abs(np.sum(k * c1) - 1.0) < 1.5e-2
