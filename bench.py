@@ -471,9 +471,11 @@ def run_filters(args):
     v = phantoms.porous((n, n, n), seed=0, device=dev)
     vox = v.numel()
     out = torch.empty_like(v)
+    hout = torch.empty((6,) + tuple(v.shape), dtype=torch.float32, device=dev)
     tiles = tiles_load(args.tiles)
     ops = [("mean_r1", lambda: h.mean(v, 1, out=out)), ("mean_r2", lambda: h.mean(v, 2, out=out)),
-           ("unsharp_s2_a1", lambda: h.unsharp(v, 2.0, 1.0, out=out)), ("sobel", lambda: h.edge(v, "sobel", out=out))]
+           ("unsharp_s2_a1", lambda: h.unsharp(v, 2.0, 1.0, out=out)), ("sobel", lambda: h.edge(v, "sobel", out=out)),
+           ("hessian_s1_6out", lambda: h.hessian(v, 1.0, out=hout))]
     for _ in range(args.warmup):
         for _, fn in ops:
             fn()
@@ -493,20 +495,23 @@ def run_filters(args):
     for name, _ in ops:
         ms = sum(a.elapsed_time(b) for a, b in events[name]) / len(events[name])
         # algorithmic bytes: read once, write once (the unsharp epilogue's
-        # read of the centre voxel is a re-read)
-        per_op[name] = {"ms": round(ms, 4), "gvox_s": round(vox / ms / 1e6, 2),
-                        "hbm_frac": round(8 * vox / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        # read of the centre voxel is a re-read); the Hessian writes 6 outputs
+        nout = 6 if name.startswith("hessian") else 1
+        per_op[name] = {"ms": round(ms, 4), "gvox_s": round(nout * vox / ms / 1e6, 2),
+                        "hbm_frac": round((4 + 4 * nout) * vox / ms / 1e6 / HBM_PEAK_GBS, 4)}
     ms_step = wall * 1000 / args.steps
     dom = max(per_op, key=lambda k: per_op[k]["ms"])
     d = per_op[dom]
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(8 * vox / d["ms"] / 1e6, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": d["hbm_frac"], "per_launch": {"bytes": 8 * vox, "ms": d["ms"]}, "traffic": None}
-    line = {"metric": METRIC, "value": round(len(ops) * vox / ms_step / 1e6, 2), "unit": "GVox/s", "n_gpus": 1,
+    nb = (4 + 4 * (6 if dom.startswith("hessian") else 1)) * vox
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(nb / d["ms"] / 1e6, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": d["hbm_frac"], "per_launch": {"bytes": nb, "ms": d["ms"]}, "traffic": None}
+    outputs = len(ops) + 5  # the Hessian has 6 outputs
+    line = {"metric": METRIC, "value": round(outputs * vox / ms_step / 1e6, 2), "unit": "GVox/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": "filters: %d^3 float32 porous phantom, mean r=1,2 + unsharp sigma 2 amount 1 + "
-                                   "Sobel magnitude" % n,
+                                   "Sobel magnitude + Hessian sigma 1 (6 outputs)" % n,
                        "voxels": vox},
             "roofline": roof, "ops": per_op, "tiles": tiles}
     if not args.no_cpu:
@@ -518,11 +523,13 @@ def run_filters(args):
         oracle.mean3d(sl, 2, method="separable")
         oracle.unsharp3d(sl, 2.0, 1.0)
         oracle.edge3d(sl, "sobel")
+        oracle.hessian3d(sl, 1.0)
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": round(4 * sl.size / dt / 1e9, 6), "unit": "GVox/s",
+        line["cpu_baseline"] = {"value": round(10 * sl.size / dt / 1e9, 6), "unit": "GVox/s",
                                 "cores": oracle.num_threads(), "kind": "oracle",
                                 "sample": "%dx%dx%d slab: separable FP64 mean r=1,2 + unsharp (direct FP64 Gaussian) "
-                                          "sigma 2 + direct FP64 Sobel, %.1f s" % (sl.shape + (dt,))}
+                                          "sigma 2 + direct FP64 Sobel + direct FP64 Hessian sigma 1, %.1f s"
+                                          % (sl.shape + (dt,))}
     return line
 
 

@@ -188,6 +188,21 @@ harpia_status harpia_unsharp3d(const void *in, harpia_dtype in_t, void *out,
                                double amount, harpia_border border,
                                const harpia_exec *ex);
 
+/* Hessian of the Gaussian-smoothed volume (Section III-C, texture feature
+ * extraction): out holds 6 float32 volumes, one after the other, with the
+ * components zz, zy, zx, yy, yx, xx.  Component ab is the separable
+ * correlation with, per axis, the taps of the derivative order that axis
+ * takes (0, 1 or 2) of the normalised sampled Gaussian w (radius as for
+ * harpia_gaussian3d): order 1 (k / s^2) w_k, order 2 ((k^2 - s^2) / s^4) w_k,
+ * computed in FP64 and rounded to FP32; reflect boundary.  in: any dtype of
+ * harpia_gaussian3d's pairs with float32 output.  Each component is one
+ * filter pass (host volumes stream six times).
+ * Errors: ARG, DTYPE, ALIAS, BUDGET, OOM, HIP, UNSUPPORTED. */
+harpia_status harpia_hessian3d(const void *in, harpia_dtype in_t, float *out,
+                               const int64_t shape[3], const double sigma[3],
+                               double truncate, harpia_border border,
+                               const harpia_exec *ex);
+
 /* Sobel / Prewitt edge enhancement (Section III-C, filtering suite):
  *   G_a = central difference [-1, 0, 1] (in[i+1] - in[i-1]) along axis a,
  *         smoothed by [1, 2, 1] (HARPIA_EDGE_SOBEL) or [1, 1, 1]

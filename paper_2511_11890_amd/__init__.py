@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import HarpiaError, harpia_plan, harpia_stats
 
-__all__ = ["gaussian", "mean", "unsharp", "edge", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
+__all__ = ["gaussian", "mean", "unsharp", "edge", "hessian", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
            "plan", "gauss_radius", "version", "HarpiaError", "harpia_stats", "Exec",
            "gaussian_backward", "morph_backward", "GaussianFn", "MorphFn", "GaussDilateFn",
            "gaussian_batched", "morph_batched", "GaussDilateBatch", "autotune_gaussian",
@@ -209,6 +209,25 @@ def unsharp(x, sigma, amount: float = 1.0, truncate: float = 3.0, out=None, out_
         _lib.check(_lib.load().harpia_unsharp3d(
             _ptr(x), ic, _ptr(out), oc, _lib.i64_3(x.shape), _lib.f64_3(_triple(sigma, float)), float(truncate),
             float(amount), _lib.HARPIA_BORDER_REFLECT, e))
+    return out
+
+
+def hessian(x, sigma, truncate: float = 3.0, out=None, ex: Exec | None = None):
+    """Hessian of the Gaussian-smoothed volume: float32 [6, nz, ny, nx] with
+    components zz, zy, zx, yy, yx, xx."""
+    _check_volume(x)
+    ic = _dtype_code(x)
+    if out is None:
+        if _is_torch(x):
+            out = _torch().empty((6,) + tuple(x.shape), dtype=_torch().float32, device=x.device,
+                                 pin_memory=(x.device.type == "cpu" and x.is_pinned()))
+        else:
+            out = np.empty((6,) + tuple(x.shape), dtype=np.float32)
+    e = _exec(x, ex)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_hessian3d(_ptr(x), ic, _ptr(out), _lib.i64_3(x.shape),
+                                                _lib.f64_3(_triple(sigma, float)), float(truncate),
+                                                _lib.HARPIA_BORDER_REFLECT, e))
     return out
 
 

@@ -308,6 +308,27 @@ harpia_status harpia_edge3d(const void *in, harpia_dtype in_t, void *out, harpia
     });
 }
 
+harpia_status harpia_hessian3d(const void *in, harpia_dtype in_t, float *out, const int64_t shape[3],
+                               const double sigma[3], double truncate, harpia_border border, const harpia_exec *ex)
+{
+    return guarded([&] {
+        if (!out) fail(HARPIA_ERR_ARG, "out is NULL");
+        if (!sigma) fail(HARPIA_ERR_ARG, "sigma is NULL");
+        check_shape(shape);
+        const Stage base = gauss_stage(in_t, HARPIA_F32, sigma, truncate);
+        const int64_t nv = voxels(shape);
+        static const int pairs[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+        for (int c = 0; c < 6; ++c) {
+            int order[3] = {0, 0, 0};
+            ++order[pairs[c][0]];
+            ++order[pairs[c][1]];
+            Stage st = base;
+            make_gauss_deriv_taps(sigma, base.r, order, st.taps);
+            run_gauss_family(in, in_t, out + c * nv, HARPIA_F32, shape, border, ex, st);
+        }
+    });
+}
+
 harpia_status harpia_unsharp3d(const void *in, harpia_dtype in_t, void *out, harpia_dtype out_t,
                                const int64_t shape[3], const double sigma[3], double truncate, double amount,
                                harpia_border border, const harpia_exec *ex)

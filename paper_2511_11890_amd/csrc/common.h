@@ -219,6 +219,8 @@ struct GaussTaps {
     float w[3][kMaxGaussRadius + 1];          // half taps w[a][|k|], FP32
     float amount;                             // unsharp mask amount a (used when unsharp != 0)
     int unsharp;                              // 1: out = (1 + a) x - a (G x); 0: out = G x
+    int odd;                                  // bit a (z 1, y 2, x 4): axis a has odd taps c_{-k} = -c_k,
+                                              // c_0 = 0, w[k] = c_k for k >= 1
 };
 
 // Fills taps in FP64 and rounds them to FP32 (host).
@@ -226,6 +228,10 @@ void make_gauss_taps(const double sigma[3], double truncate, GaussTaps &t);
 void make_gauss_taps_r(const double sigma[3], const int radius[3], GaussTaps &t);
 // Uniform taps 1 / (2 r + 1) per axis (the mean filter), in FP64 then FP32.
 void make_mean_taps(const int radius[3], GaussTaps &t);
+// Correlation taps of the order[a]-th derivative (0, 1, 2) of the Gaussian
+// smoothing along each axis, from the FP64 normalised taps w:
+// order 1: (k / s^2) w_k (odd), order 2: ((k^2 - s^2) / s^4) w_k.
+void make_gauss_deriv_taps(const double sigma[3], const int radius[3], const int order[3], GaussTaps &t);
 // As make_gauss_taps_r, with axis `d_axis` replaced by d w / d sigma (radius
 // held fixed): w_k (k^2 - sum_j w_j j^2) / sigma^3, in FP64.
 void make_gauss_dtaps_r(const double sigma[3], const int radius[3], int d_axis, GaussTaps &t);
@@ -248,7 +254,9 @@ bool launch_gaussian(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t,
 bool launch_edge(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t, int kind, hipStream_t s);
 // Scratch bytes the Gaussian needs for an output region of `out_e` voxels
 // (0 for the fused kernel).
-size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3]);
+// fused = false: the bytes of the unfused passes even where a fused kernel
+// exists (odd taps are fused for float32 -> float32 only).
+size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3], bool fused = true);
 
 struct MorphSpec {
     int op;              // 0 erode (min), 1 dilate (max)

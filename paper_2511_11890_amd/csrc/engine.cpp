@@ -167,7 +167,8 @@ Region volume_region(const void *base, size_t es, const int64_t n[3], const int6
 size_t stage_scratch(const Stage &st, const int64_t ext[3])
 {
     if (st.kind != Stage::GAUSS) return 0;
-    return gaussian_scratch_bytes(ext, st.r);
+    const bool fused = !st.taps.odd || (st.in_t == HARPIA_F32 && st.out_t == HARPIA_F32);
+    return gaussian_scratch_bytes(ext, st.r, fused);
 }
 
 void launch_stage(const Stage &st, const Region &in, const Region &out, const Region *out2, const int64_t n[3],

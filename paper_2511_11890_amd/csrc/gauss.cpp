@@ -100,9 +100,9 @@ int64_t launch_gauss_dot_batched(const BatchDesc &d, harpia_dtype in_t, const Ga
 
 int64_t gauss_batched_max_partials() { return 8192; }
 
-size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3])
+size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3], bool fused)
 {
-    if (r[0] == r[1] && r[1] == r[2] && r[0] >= 1 && r[0] <= kGaussFusedMaxR) return 0;
+    if (fused && r[0] == r[1] && r[1] == r[2] && r[0] >= 1 && r[0] <= kGaussFusedMaxR) return 0;
     // worst case input region: output extent + 2r per axis
     const int64_t iz = out_e[0] + 2 * r[0], iy = out_e[1] + 2 * r[1];
     return (size_t)((iz * iy * out_e[2] + iz * out_e[1] * out_e[2]) * (int64_t)sizeof(float));
@@ -112,6 +112,7 @@ void make_mean_taps(const int radius[3], GaussTaps &t)
 {
     t.amount = 0.f;
     t.unsharp = 0;
+    t.odd = 0;
     for (int ax = 0; ax < 3; ++ax) {
         const int r = radius[ax];
         t.r[ax] = r;
@@ -120,10 +121,38 @@ void make_mean_taps(const int radius[3], GaussTaps &t)
     }
 }
 
+void make_gauss_deriv_taps(const double sigma[3], const int radius[3], const int order[3], GaussTaps &t)
+{
+    t.amount = 0.f;
+    t.unsharp = 0;
+    t.odd = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int r = radius[ax];
+        t.r[ax] = r;
+        const double s2 = sigma[ax] * sigma[ax];
+        double e[kMaxGaussRadius + 1];
+        double total = 0.0;
+        for (int k = 0; k <= r; ++k) {
+            e[k] = std::exp(-((double)k * (double)k) / (2.0 * s2));
+            total += (k == 0) ? e[k] : 2.0 * e[k];
+        }
+        for (int k = 0; k <= kMaxGaussRadius; ++k) {
+            double c = 0.0;
+            if (k <= r) {
+                const double w = e[k] / total;
+                c = order[ax] == 0 ? w : (order[ax] == 1 ? (double)k / s2 * w : ((double)k * k - s2) / (s2 * s2) * w);
+            }
+            t.w[ax][k] = (float)c;
+        }
+        if (order[ax] == 1) t.odd |= 1 << ax;
+    }
+}
+
 void make_gauss_taps_r(const double sigma[3], const int radius[3], GaussTaps &t)
 {
     t.amount = 0.f;
     t.unsharp = 0;
+    t.odd = 0;
     for (int ax = 0; ax < 3; ++ax) {
         const int r = radius[ax];
         t.r[ax] = r;

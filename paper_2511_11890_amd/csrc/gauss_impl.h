@@ -142,7 +142,10 @@ struct DotOut {
 
 // One tile of the fused Gaussian: output columns [x0, x0 + kTX) x
 // [y0, y0 + kTY) of the output region, slices [zo0, zo0 + zlen).
-template <typename Tin, int R, int D, class Out>
+// PAR: bit a set (z = 1, y = 2, x = 4) when the taps of axis a are odd,
+// c_{-k} = -c_k and c_0 = 0, with w[k] = c_k for k >= 1 (a first-derivative
+// correlation, v[i + k] weighted by c_k); even taps otherwise.
+template <typename Tin, int R, int D, class Out, int PAR = 0>
 __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &taps, int zlen, int bx, int by,
                                            int bz, Out &out)
 {
@@ -271,16 +274,24 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
                 float t[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    float sacc = wx[0] * h[c + R];
+                    float sacc;
+                    if constexpr (PAR & 4) {
+                        sacc = 0.f;
 #pragma unroll
-                    for (int k = 1; k <= R; ++k) sacc = fmaf(wx[k], h[c + R - k] + h[c + R + k], sacc);
+                        for (int k = 1; k <= R; ++k) sacc = fmaf(wx[k], h[c + R + k] - h[c + R - k], sacc);
+                    } else {
+                        sacc = wx[0] * h[c + R];
+#pragma unroll
+                        for (int k = 1; k <= R; ++k) sacc = fmaf(wx[k], h[c + R - k] + h[c + R + k], sacc);
+                    }
                     t[c] = sacc;
                 }
-                // z pass: slice j = i - 1 feeds output j + d with weight w|d|
+                // z pass: slice j = i - 1 feeds output o = j + d with the tap
+                // c_{j - o} = c_{-d} (w|d| for even taps)
                 static_for<P>([&](auto DD) {
                     constexpr int d = decltype(DD)::value - R;
                     constexpr int sl = (u - 1 + d + 2 * P) % P;
-                    const float wd = wz[d < 0 ? -d : d];
+                    const float wd = (PAR & 1) ? (d == 0 ? 0.f : (d < 0 ? wz[-d] : -wz[d])) : wz[d < 0 ? -d : d];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) acc[sl][c] = (d == R) ? wd * t[c] : fmaf(wd, t[c], acc[sl][c]);
                 });
@@ -299,9 +310,16 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
                     for (int j = 0; j < kMY + 2 * R; ++j) v[j] = p[(rg * kMY + j) * PW + col];
 #pragma unroll
                     for (int m = 0; m < kMY; ++m) {
-                        float sacc = wy[0] * v[m + R];
+                        float sacc;
+                        if constexpr (PAR & 2) {
+                            sacc = 0.f;
 #pragma unroll
-                        for (int k = 1; k <= R; ++k) sacc = fmaf(wy[k], v[m + R - k] + v[m + R + k], sacc);
+                            for (int k = 1; k <= R; ++k) sacc = fmaf(wy[k], v[m + R + k] - v[m + R - k], sacc);
+                        } else {
+                            sacc = wy[0] * v[m + R];
+#pragma unroll
+                            for (int k = 1; k <= R; ++k) sacc = fmaf(wy[k], v[m + R - k] + v[m + R + k], sacc);
+                        }
                         q[(rg * kMY + m) * QP + col] = sacc;
                     }
                 }
@@ -579,14 +597,14 @@ __device__ __forceinline__ void tile_of_block(uint32_t b, int tiles_x, int tiles
     bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
 }
 
-template <typename Tin, typename Tout, int R, bool UNSHARP = false, int D = gauss_prefetch_depth(R)>
+template <typename Tin, typename Tout, int R, bool UNSHARP = false, int PAR = 0, int D = gauss_prefetch_depth(R)>
 __global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps taps, int zlen, int tiles_x,
                                                           int tiles_y)
 {
     int bx, by, bz;
     tile_of_block(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, bx, by, bz);
     StoreOut<Tin, Tout, UNSHARP> out{static_cast<Tout *>(a.out), static_cast<const Tin *>(a.in), taps.amount};
-    gauss_tile<Tin, R, D>(a, taps, zlen, bx, by, bz, out);
+    gauss_tile<Tin, R, D, StoreOut<Tin, Tout, UNSHARP>, PAR>(a, taps, zlen, bx, by, bz, out);
 }
 
 
@@ -653,6 +671,7 @@ __global__ __launch_bounds__(256) void gauss_pass_kernel(const Tin *src, int64_t
 {
     const int64_t total = ez * ey * ex;
     const int r = taps.r[axis];
+    const bool odd = (taps.odd >> axis) & 1;  // c_{-k} = -c_k, c_0 = 0
     for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
          id += (int64_t)gridDim.x * blockDim.x) {
         const int64_t x = id % ex, y = (id / ex) % ey, z = id / (ex * ey);
@@ -662,31 +681,47 @@ __global__ __launch_bounds__(256) void gauss_pass_kernel(const Tin *src, int64_t
             int64_t c[3] = {g[0], g[1], g[2]};
             c[axis] = reflect_index(g[axis] + k, n_axis);
             const int64_t off = (c[0] - s_oz) * s_sz + (c[1] - s_oy) * s_sy + (c[2] - s_ox);
-            sacc = fmaf(taps.w[axis][k < 0 ? -k : k], to_f32(src[off]), sacc);
+            float wk = taps.w[axis][k < 0 ? -k : k];
+            if (odd) wk = k == 0 ? 0.f : (k < 0 ? -wk : wk);
+            sacc = fmaf(wk, to_f32(src[off]), sacc);
         }
         dst[z * d_sz + y * d_sy + x] = from_f32<Tout>(sacc);
     }
 }
 
-template <typename Tin, typename Tout, int R, bool UNSHARP>
+template <typename Tin, typename Tout, int R, bool UNSHARP, int PAR = 0>
 void launch_fused_u(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
-    static const int64_t cap = resident_blocks(gauss_fused_kernel<Tin, Tout, R, UNSHARP>, kNT);
+    static const int64_t cap = resident_blocks(gauss_fused_kernel<Tin, Tout, R, UNSHARP, PAR>, kNT);
     Tile t;
-    const int code = tune_type_code<Tin>() * 8 + tune_type_code<Tout>() + (UNSHARP ? 64 : 0);
+    const int code = tune_type_code<Tin>() * 8 + tune_type_code<Tout>() + (UNSHARP ? 64 : 0) + PAR * 128;
     const bool tuned = tune_lookup(TF_GAUSS, tune_key_volume(TF_GAUSS, R, code, a.out_e), t);
     const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0);
-    hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R, UNSHARP>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a,
-                       taps, g.zlen, g.tiles_x, g.tiles_y);
+    hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R, UNSHARP, PAR>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s,
+                       a, taps, g.zlen, g.tiles_x, g.tiles_y);
 }
 
+// Odd taps (derivative filters: the mixed Hessian components) are built for
+// float32 -> float32 only; other pairs take the unfused path.
 template <typename Tin, typename Tout, int R>
-void launch_fused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
+bool launch_fused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
-    if (taps.unsharp)
+    if (taps.unsharp) {
         launch_fused_u<Tin, Tout, R, true>(a, taps, s);
-    else
-        launch_fused_u<Tin, Tout, R, false>(a, taps, s);
+        return true;
+    }
+    if constexpr (std::is_same<Tin, float>::value && std::is_same<Tout, float>::value) {
+        switch (taps.odd) {
+        case 0: launch_fused_u<Tin, Tout, R, false, 0>(a, taps, s); return true;
+        case 3: launch_fused_u<Tin, Tout, R, false, 3>(a, taps, s); return true;
+        case 5: launch_fused_u<Tin, Tout, R, false, 5>(a, taps, s); return true;
+        case 6: launch_fused_u<Tin, Tout, R, false, 6>(a, taps, s); return true;
+        default: return false;
+        }
+    }
+    if (taps.odd) return false;
+    launch_fused_u<Tin, Tout, R, false>(a, taps, s);
+    return true;
 }
 
 template <typename Tin, int R>
@@ -731,10 +766,9 @@ template <typename Tin, typename Tout>
 bool dispatch_fused(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
     switch (r) {
-#define HARPIA_CASE(RR)                              \
-    case RR:                                         \
-        launch_fused<Tin, Tout, RR>(a, taps, s);     \
-        return true;
+#define HARPIA_CASE(RR) \
+    case RR:            \
+        return launch_fused<Tin, Tout, RR>(a, taps, s);
         HARPIA_CASE(1)
         HARPIA_CASE(2)
         HARPIA_CASE(3)
@@ -796,9 +830,11 @@ void launch_unfused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, fl
 template <typename Tin, typename Tout>
 bool run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes)
 {
-    if (fused_ok(taps, a)) return dispatch_fused<Tin, Tout>(taps.r[0], a, taps, s);
+    if (fused_ok(taps, a) && dispatch_fused<Tin, Tout>(taps.r[0], a, taps, s)) return true;
     if (taps.unsharp) return false;  // the unsharp epilogue lives in the fused kernel
-    const int64_t need = (int64_t)gaussian_scratch_bytes(a.out_e, taps.r);
+    // the unfused passes, whatever the radii (odd taps of other dtype pairs,
+    // slices too large for the fused kernel's 32-bit offsets)
+    const int64_t need = (int64_t)gaussian_scratch_bytes(a.out_e, taps.r, false);
     if (scratch == nullptr || (int64_t)scratch_bytes < need) return false;
     launch_unfused<Tin, Tout>(a, taps, s, static_cast<float *>(scratch));
     return true;

@@ -194,3 +194,48 @@ def test_edge_u16_chunked_equals_resident(dev):
     v64 = to_np64(v)
     assert_gauss_close(to_np64(res), oracle.edge3d(v64, "prewitt"), _edge_scale(v64, "prewitt"), FP32_GAUSS_TOL,
                        "u16")
+
+
+# ----------------------------------------------------------------- Hessian
+# Component ab errs by at most 1e-5 * (|c_z| x |c_y| x |c_x|) * |v| (the
+# separable correlation with the absolute taps).
+
+def _hess_scale(v64, sigma):
+    s = (sigma,) * 3 if np.ndim(sigma) == 0 else tuple(sigma)
+    r = [oracle.gauss_radius(si) for si in s]
+    out = []
+    for a, b in oracle.HESSIAN_PAIRS:
+        order = [0, 0, 0]
+        order[a] += 1
+        order[b] += 1
+        taps = [np.abs(oracle.gauss_deriv_taps(s[i], r[i], order[i])) for i in range(3)]
+        out.append(oracle.conv3d(np.abs(v64), *taps, method="separable"))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("sigma", [1.0, 2.0, (1.0, 1.5, 0.8)])
+def test_hessian_f32(dev, sigma):
+    v = phantoms.porous(SHAPE, seed=103).numpy()
+    print("hessian f32", SHAPE, sigma, flush=True)
+    got = h.hessian(torch.from_numpy(v).to(dev), sigma)
+    torch.cuda.synchronize()
+    assert got.shape == (6,) + SHAPE
+    v64 = v.astype(np.float64)
+    assert_gauss_close(to_np64(got), oracle.hessian3d(v64, sigma), _hess_scale(v64, sigma), FP32_GAUSS_TOL,
+                       "sigma=%s" % (sigma,))
+
+
+def test_hessian_u16_and_chunked(dev):
+    # u16 input: odd components take the unfused passes
+    v = phantoms.porous_u16((20, 33, 70), seed=104)
+    res = h.hessian(v.to(dev), 1.0)
+    host = h.hessian(v.pin_memory(), 1.0, ex=h.Exec(budget=4 << 20))
+    torch.cuda.synchronize()
+    v64 = to_np64(v)
+    assert_gauss_close(to_np64(res), oracle.hessian3d(v64, 1.0), _hess_scale(v64, 1.0), FP32_GAUSS_TOL, "u16")
+    assert torch.equal(host, res.cpu())
+    x = torch.from_numpy(phantoms.porous((20, 33, 70), seed=105).numpy()).to(dev)
+    a = h.hessian(x, 1.5)
+    b = h.hessian(x, 1.5, ex=h.Exec(force_chunked=True, chunk=(8, 16, 64), budget=64 << 20))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
