@@ -472,7 +472,14 @@ def run_filters(args):
     vox = v.numel()
     out = torch.empty_like(v)
     hout = torch.empty((6,) + tuple(v.shape), dtype=torch.float32, device=dev)
-    tiles = tiles_load(args.tiles)
+    if args.tune:
+        # the mean filter runs the fused kernel of radius r (sigma 0.34 and
+        # 0.5 resolve to r = 1 and 2: same kernel, same workload key)
+        tuned = {"r%d" % r: h.autotune_gaussian(v, sg, out=out) for r, sg in ((1, 0.34), (2, 0.5))}
+        tiles = tiles_merge_save(args.tiles)
+        tiles["report"] = tuned
+    else:
+        tiles = tiles_load(args.tiles)
     ops = [("mean_r1", lambda: h.mean(v, 1, out=out)), ("mean_r2", lambda: h.mean(v, 2, out=out)),
            ("unsharp_s2_a1", lambda: h.unsharp(v, 2.0, 1.0, out=out)), ("sobel", lambda: h.edge(v, "sobel", out=out)),
            ("hessian_s1_6out", lambda: h.hessian(v, 1.0, out=hout))]
@@ -544,7 +551,8 @@ def main():
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one plain device copy of the volume (counter reference)")
     ap.add_argument("--tune", action="store_true",
-                    help="resident / batched: run the autotuner on the ops first and merge its tiles into --tiles")
+                    help="resident / batched / filters: run the autotuner on the ops first and merge its tiles "
+                         "into --tiles")
     ap.add_argument("--tiles", default=TILES, help="tile file of the autotuner (loaded if present)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("CSV_DIR", "COMMAND", "TITLE"),
                     help="print a markdown summary of a rocprofv3 --stats csv run and exit (no GPU)")
