@@ -323,6 +323,39 @@ def hessian3d(v, sigma, truncate: float = 3.0) -> np.ndarray:
     return np.stack(out)
 
 
+THRESHOLD_METHODS = ("mean", "gaussian", "niblack", "sauvola")
+
+
+def local_threshold3d(v, method: str, radius=1, sigma: float = 1.0, k: float = 0.0, r_param: float = 128.0,
+                      offset: float = 0.0, return_t: bool = False):
+    """Local thresholds of the label-editing module (Section III-C), each
+    voxel against a threshold T from its neighbourhood (reflect boundary):
+      mean:     T = m - offset, m the (2r+1)-box mean;
+      gaussian: T = G_sigma v - offset;
+      niblack:  T = m + k s, s the box standard deviation
+                sqrt(mean(v^2) - m^2) (population form);
+      sauvola:  T = m (1 + k (s / r_param - 1)).
+    Returns uint8 (v > T), and T with return_t."""
+    v = _f64(v)
+    if method == "gaussian":
+        t = gaussian3d(v, sigma, method="direct") - offset
+    else:
+        m = mean3d(v, radius, method="direct")
+        if method == "mean":
+            t = m - offset
+        else:
+            q = mean3d(v * v, radius, method="direct")
+            sd = np.sqrt(np.maximum(q - m * m, 0.0))
+            if method == "niblack":
+                t = m + k * sd
+            elif method == "sauvola":
+                t = m * (1.0 + k * (sd / r_param - 1.0))
+            else:
+                raise ValueError("unknown method")
+    out = (v > t).astype(np.uint8)
+    return (out, t) if return_t else out
+
+
 def opening3d(v, se="box", radius=1):
     """Opening = dilation of the erosion, each over the full volume."""
     return dilate3d(erode3d(v, se, radius), se, radius)

@@ -623,3 +623,38 @@ def test_deriv_taps_moments():
         # truncation at 3 sigma keeps M2 within 1.5 % of s^2, so the
         # derivative of a unit ramp is close to 1
         assert abs(np.sum(k * c1) - 1.0) < 1.5e-2
+
+
+# -------------------------------------------------------- local thresholds
+
+@pytest.mark.parametrize("method", ["mean", "niblack", "sauvola", "gaussian"])
+def test_local_threshold_equals_scipy_statistics(method):
+    v = _rng(90).uniform(0, 200, size=(9, 10, 11))
+    r, k, R, c = 2, -0.2 if method == "niblack" else 0.3, 100.0, 3.0
+    out, t = oracle.local_threshold3d(v, method, radius=r, sigma=1.5, k=k, r_param=R, offset=c, return_t=True)
+    m = ndi.uniform_filter(v, size=2 * r + 1, mode="reflect")
+    sd = np.sqrt(np.maximum(ndi.uniform_filter(v * v, size=2 * r + 1, mode="reflect") - m * m, 0))
+    want = {"mean": m - c, "niblack": m + k * sd, "sauvola": m * (1 + k * (sd / R - 1)),
+            "gaussian": ndi.gaussian_filter(v, 1.5, mode="reflect", truncate=3.0) - c}[method]
+    np.testing.assert_allclose(t, want, rtol=1e-12, atol=1e-9)
+    np.testing.assert_array_equal(out, (v > want).astype(np.uint8))
+
+
+def test_local_threshold_closed_forms():
+    # constant volume: s = 0, so Niblack's T equals v (strict: all 0), the
+    # mean threshold with a positive offset keeps everything, Sauvola with
+    # 0 < k < 1 keeps a positive constant
+    c = np.full((5, 6, 7), 40.0)
+    assert oracle.local_threshold3d(c, "niblack", 2, k=-0.2).sum() == 0
+    assert oracle.local_threshold3d(c, "mean", 2, offset=1.0).all()
+    assert oracle.local_threshold3d(c, "sauvola", 2, k=0.5, r_param=128.0).all()
+    # a single bright voxel in a dark box: above the local mean there only
+    v = np.zeros((7, 7, 7))
+    v[3, 3, 3] = 100.0
+    out = oracle.local_threshold3d(v, "mean", 1)
+    assert out.sum() == 1 and out[3, 3, 3] == 1
+    # box standard deviation of a two-valued window, by hand
+    w = np.zeros((3, 3, 3))
+    w[0] = 27.0  # one face of 9 voxels at 27, the rest 0: m = 9, s = sqrt(243 - 81)
+    _, t = oracle.local_threshold3d(w, "niblack", 1, k=1.0, return_t=True)
+    assert abs(t[1, 1, 1] - (9.0 + math.sqrt(162.0))) < 1e-12
