@@ -472,6 +472,7 @@ def run_filters(args):
     vox = v.numel()
     out = torch.empty_like(v)
     hout = torch.empty((6,) + tuple(v.shape), dtype=torch.float32, device=dev)
+    bout = torch.empty(tuple(v.shape), dtype=torch.uint8, device=dev)
     if args.tune:
         # the mean filter runs the fused kernel of radius r (sigma 0.34 and
         # 0.5 resolve to r = 1 and 2: same kernel, same workload key)
@@ -482,7 +483,8 @@ def run_filters(args):
         tiles = tiles_load(args.tiles)
     ops = [("mean_r1", lambda: h.mean(v, 1, out=out)), ("mean_r2", lambda: h.mean(v, 2, out=out)),
            ("unsharp_s2_a1", lambda: h.unsharp(v, 2.0, 1.0, out=out)), ("sobel", lambda: h.edge(v, "sobel", out=out)),
-           ("hessian_s1_6out", lambda: h.hessian(v, 1.0, out=hout))]
+           ("hessian_s1_6out", lambda: h.hessian(v, 1.0, out=hout)),
+           ("niblack_r2", lambda: h.local_threshold(v, "niblack", radius=2, k=-0.2, out=bout))]
     for _ in range(args.warmup):
         for _, fn in ops:
             fn()
@@ -504,8 +506,9 @@ def run_filters(args):
         # algorithmic bytes: read once, write once (the unsharp epilogue's
         # read of the centre voxel is a re-read); the Hessian writes 6 outputs
         nout = 6 if name.startswith("hessian") else 1
+        alg = (4 + 4 * nout) if not name.startswith("niblack") else 5  # the threshold writes a byte
         per_op[name] = {"ms": round(ms, 4), "gvox_s": round(nout * vox / ms / 1e6, 2),
-                        "hbm_frac": round((4 + 4 * nout) * vox / ms / 1e6 / HBM_PEAK_GBS, 4)}
+                        "hbm_frac": round(alg * vox / ms / 1e6 / HBM_PEAK_GBS, 4)}
     ms_step = wall * 1000 / args.steps
     dom = max(per_op, key=lambda k: per_op[k]["ms"])
     d = per_op[dom]
@@ -518,7 +521,7 @@ def run_filters(args):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": "filters: %d^3 float32 porous phantom, mean r=1,2 + unsharp sigma 2 amount 1 + "
-                                   "Sobel magnitude + Hessian sigma 1 (6 outputs)" % n,
+                                   "Sobel magnitude + Hessian sigma 1 (6 outputs) + Niblack r=2" % n,
                        "voxels": vox},
             "roofline": roof, "ops": per_op, "tiles": tiles}
     if not args.no_cpu:
@@ -531,11 +534,12 @@ def run_filters(args):
         oracle.unsharp3d(sl, 2.0, 1.0)
         oracle.edge3d(sl, "sobel")
         oracle.hessian3d(sl, 1.0)
+        oracle.local_threshold3d(sl, "niblack", 2, k=-0.2)
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": round(10 * sl.size / dt / 1e9, 6), "unit": "GVox/s",
+        line["cpu_baseline"] = {"value": round(11 * sl.size / dt / 1e9, 6), "unit": "GVox/s",
                                 "cores": oracle.num_threads(), "kind": "oracle",
                                 "sample": "%dx%dx%d slab: separable FP64 mean r=1,2 + unsharp (direct FP64 Gaussian) "
-                                          "sigma 2 + direct FP64 Sobel + direct FP64 Hessian sigma 1, %.1f s"
+                                          "sigma 2 + direct FP64 Sobel + direct FP64 Hessian sigma 1 + Niblack r=2, %.1f s"
                                           % (sl.shape + (dt,))}
     return line
 

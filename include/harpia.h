@@ -203,6 +203,35 @@ harpia_status harpia_hessian3d(const void *in, harpia_dtype in_t, float *out,
                                double truncate, harpia_border border,
                                const harpia_exec *ex);
 
+/* Local thresholds (Section III-C, threshold algorithms of the label
+ * editing module): out[p] = 1 if in[p] > T[p] else 0 (uint8), with
+ *   HARPIA_THRESHOLD_MEAN:     T = m - offset,
+ *   HARPIA_THRESHOLD_GAUSSIAN: T = G_sigma(in) - offset (taps and radius
+ *                              as for harpia_gaussian3d with `truncate`),
+ *   HARPIA_THRESHOLD_NIBLACK:  T = m + k s,
+ *   HARPIA_THRESHOLD_SAUVOLA:  T = m (1 + k (s / r_param - 1)),
+ * m the mean and s = sqrt(mean(in^2) - m^2) the standard deviation over the
+ * (2 radius + 1)^3 box, reflect boundary, FP32 arithmetic (a voxel within
+ * FP32 rounding of its threshold may fall on either side).
+ * radius: 1..12 for mean, 1..6 for Niblack and Sauvola (unused for the
+ * Gaussian, whose radius comes from sigma: 1..12).  t: U8, U16 or F32.
+ * Errors: ARG, DTYPE, ALIAS, BUDGET, OOM, HIP, UNSUPPORTED. */
+typedef enum {
+    HARPIA_THRESHOLD_MEAN = 0,
+    HARPIA_THRESHOLD_GAUSSIAN = 1,
+    HARPIA_THRESHOLD_NIBLACK = 2,
+    HARPIA_THRESHOLD_SAUVOLA = 3
+} harpia_threshold_method;
+
+harpia_status harpia_local_threshold3d(const void *in, harpia_dtype t,
+                                       uint8_t *out, const int64_t shape[3],
+                                       harpia_threshold_method method,
+                                       int32_t radius, double sigma,
+                                       double truncate, double k,
+                                       double r_param, double offset,
+                                       harpia_border border,
+                                       const harpia_exec *ex);
+
 /* Sobel / Prewitt edge enhancement (Section III-C, filtering suite):
  *   G_a = central difference [-1, 0, 1] (in[i+1] - in[i-1]) along axis a,
  *         smoothed by [1, 2, 1] (HARPIA_EDGE_SOBEL) or [1, 1, 1]

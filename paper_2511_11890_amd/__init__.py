@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import HarpiaError, harpia_plan, harpia_stats
 
-__all__ = ["gaussian", "mean", "unsharp", "edge", "hessian", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
+__all__ = ["gaussian", "mean", "unsharp", "edge", "hessian", "local_threshold", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
            "plan", "gauss_radius", "version", "HarpiaError", "harpia_stats", "Exec",
            "gaussian_backward", "morph_backward", "GaussianFn", "MorphFn", "GaussDilateFn",
            "gaussian_batched", "morph_batched", "GaussDilateBatch", "autotune_gaussian",
@@ -209,6 +209,25 @@ def unsharp(x, sigma, amount: float = 1.0, truncate: float = 3.0, out=None, out_
         _lib.check(_lib.load().harpia_unsharp3d(
             _ptr(x), ic, _ptr(out), oc, _lib.i64_3(x.shape), _lib.f64_3(_triple(sigma, float)), float(truncate),
             float(amount), _lib.HARPIA_BORDER_REFLECT, e))
+    return out
+
+
+def local_threshold(x, method: str = "mean", radius: int = 1, sigma: float = 1.0, k: float = 0.0,
+                    r_param: float = 128.0, offset: float = 0.0, truncate: float = 3.0, out=None,
+                    ex: Exec | None = None):
+    """Local threshold (mean, gaussian, niblack, sauvola): uint8 (x > T)."""
+    _check_volume(x)
+    ic = _dtype_code(x)
+    if out is None:
+        out = _empty_like(x, _lib.HARPIA_U8)
+    else:
+        _check_volume(out)
+    e = _exec(x, ex)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_local_threshold3d(
+            _ptr(x), ic, _ptr(out), _lib.i64_3(x.shape),
+            {"mean": 0, "gaussian": 1, "niblack": 2, "sauvola": 3}[method], int(radius), float(sigma),
+            float(truncate), float(k), float(r_param), float(offset), _lib.HARPIA_BORDER_REFLECT, e))
     return out
 
 

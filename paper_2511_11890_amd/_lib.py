@@ -98,6 +98,9 @@ SIGNATURES = {
     "harpia_gaussian3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _I64_3, _F64_3,
                                          ctypes.c_double, ctypes.c_int, _ex]),
     "harpia_mean3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _I64_3, _I32_3, ctypes.c_int, _ex]),
+    "harpia_local_threshold3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _I64_3, ctypes.c_int, ctypes.c_int32,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_int, _ex]),
     "harpia_hessian3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _I64_3, _F64_3, ctypes.c_double, ctypes.c_int,
                                         _ex]),
     "harpia_edge3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _I64_3, ctypes.c_int, ctypes.c_int, _ex]),

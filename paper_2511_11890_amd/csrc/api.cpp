@@ -292,6 +292,57 @@ harpia_status harpia_mean3d(const void *in, harpia_dtype in_t, void *out, harpia
     });
 }
 
+harpia_status harpia_local_threshold3d(const void *in, harpia_dtype t, uint8_t *out, const int64_t shape[3],
+                                       harpia_threshold_method method, int32_t radius, double sigma, double truncate,
+                                       double k, double r_param, double offset, harpia_border border,
+                                       const harpia_exec *ex)
+{
+    return guarded([&] {
+        if (!in || !out) fail(HARPIA_ERR_ARG, "in / out is NULL");
+        check_shape(shape);
+        check_exec(ex);
+        if (border != HARPIA_BORDER_REFLECT) fail(HARPIA_ERR_ARG, "only the reflect border is supported");
+        if (method < HARPIA_THRESHOLD_MEAN || method > HARPIA_THRESHOLD_SAUVOLA)
+            fail(HARPIA_ERR_ARG, "unknown threshold method");
+        if (t != HARPIA_U8 && t != HARPIA_U16 && t != HARPIA_F32)
+            fail(HARPIA_ERR_DTYPE, "local thresholds take u8, u16 or f32 volumes");
+        if (!std::isfinite(k) || !std::isfinite(offset) || !(r_param > 0.0) || !std::isfinite(r_param))
+            fail(HARPIA_ERR_ARG, "k and offset must be finite, r_param finite and > 0");
+        Stage st;
+        std::memset(&st, 0, sizeof(st));
+        st.kind = Stage::THRESH;
+        st.in_t = t;
+        st.out_t = HARPIA_U8;
+        if (method == HARPIA_THRESHOLD_GAUSSIAN) {
+            const double sg[3] = {sigma, sigma, sigma};
+            const Stage g = gauss_stage(t == HARPIA_F32 ? HARPIA_F32 : HARPIA_U16, HARPIA_F32, sg, truncate);
+            for (int a = 0; a < 3; ++a) st.r[a] = g.r[a];
+            st.taps = g.taps;
+        } else {
+            int r[3] = {radius, radius, radius};
+            make_mean_taps(r, st.taps);
+            for (int a = 0; a < 3; ++a) st.r[a] = radius;
+        }
+        const int maxr = local_threshold_max_radius((int)method);
+        if (st.r[0] < 1 || st.r[0] > maxr)
+            fail(HARPIA_ERR_UNSUPPORTED, "threshold radius must be in [1, " + std::to_string(maxr) + "]");
+        st.thr_method = (int)method;
+        st.thr_k = (float)k;
+        st.thr_r = (float)r_param;
+        st.thr_offset = (float)offset;
+        const int64_t nv = voxels(shape);
+        check_alias(in, nv * dtype_size(t), out, nv);
+        Job job;
+        job.in = in;
+        job.out = out;
+        job.out2 = nullptr;
+        for (int a = 0; a < 3; ++a) job.n[a] = shape[a];
+        job.stages.push_back(st);
+        job.ex = ex;
+        run_job(job);
+    });
+}
+
 harpia_status harpia_edge3d(const void *in, harpia_dtype in_t, void *out, harpia_dtype out_t,
                             const int64_t shape[3], harpia_edge kind, harpia_border border, const harpia_exec *ex)
 {

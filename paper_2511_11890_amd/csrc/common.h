@@ -249,6 +249,11 @@ int64_t gauss_sigma3_blocks_bound(const int64_t n[3]);
 bool launch_gaussian(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t,
                      const GaussTaps &taps, hipStream_t s, void *scratch,
                      size_t scratch_bytes);
+// Local threshold of one chunk (uint8 out); taps hold the box or Gaussian
+// weights.  Returns false for unsupported dtypes / radii.
+bool launch_local_threshold(const ChunkArgs &a, harpia_dtype in_t, const GaussTaps &taps, int method, float k,
+                            float r_param, float offset, hipStream_t s);
+int local_threshold_max_radius(int method);
 // Sobel (kind 0) / Prewitt (kind 1) gradient magnitude of one chunk (radius
 // 1 halo); dtype pairs as for the Gaussian.
 bool launch_edge(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t, int kind, hipStream_t s);

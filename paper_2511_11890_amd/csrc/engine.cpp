@@ -181,6 +181,9 @@ void launch_stage(const Stage &st, const Region &in, const Region &out, const Re
     case Stage::MORPH: ok = launch_morph_ex(a, st.in_t, st.morph, false, nullptr, s); break;
     case Stage::MORPH_BOTH: ok = launch_morph_ex(a, st.in_t, st.morph, true, out2, s); break;
     case Stage::EDGE: ok = launch_edge(a, st.in_t, st.out_t, st.edge, s); break;
+    case Stage::THRESH:
+        ok = launch_local_threshold(a, st.in_t, st.taps, st.thr_method, st.thr_k, st.thr_r, st.thr_offset, s);
+        break;
     }
     if (!ok) fail(HARPIA_ERR_UNSUPPORTED, "no kernel for this dtype / radius combination");
     check_hip(hipGetLastError(), "kernel launch");

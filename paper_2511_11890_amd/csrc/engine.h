@@ -11,12 +11,14 @@ namespace harpia {
 
 // One filter step of a pipeline.
 struct Stage {
-    enum Kind { GAUSS, MORPH, MORPH_BOTH, EDGE } kind;
+    enum Kind { GAUSS, MORPH, MORPH_BOTH, EDGE, THRESH } kind;
     harpia_dtype in_t, out_t;  // element types read and written by the step
     int r[3];                  // radius per axis (the halo this step needs)
     GaussTaps taps;            // GAUSS
     MorphSpec morph;           // MORPH / MORPH_BOTH
     int edge;                  // EDGE: harpia_edge (Sobel / Prewitt)
+    int thr_method;            // THRESH: harpia_threshold_method (weights in taps)
+    float thr_k, thr_r, thr_offset;
 };
 
 struct Job {

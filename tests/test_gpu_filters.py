@@ -239,3 +239,71 @@ def test_hessian_u16_and_chunked(dev):
     b = h.hessian(x, 1.5, ex=h.Exec(force_chunked=True, chunk=(8, 16, 64), budget=64 << 20))
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+# -------------------------------------------------------- local thresholds
+# The decision v > T is taken in FP32 on the GPU and in FP64 by the oracle:
+# the two must agree wherever |v - T| exceeds the FP32 error bound of T
+# (from the bounds of the mean m and of s = sqrt(q - m^2)), and that band
+# must hold few voxels.
+
+def _thr_band(v64, method, r, sigma, k, R, c):
+    av = np.abs(v64)
+    if method == "gaussian":
+        return 2e-5 * (gauss_scale(v64, sigma) + abs(c)) + 1e-30
+    m_scale = oracle.mean3d(av, r, method="separable")
+    dm = 2e-5 * (m_scale + abs(c))
+    if method == "mean":
+        return dm + 1e-30
+    q_scale = oracle.mean3d(av * av, r, method="separable")
+    m = oracle.mean3d(v64, r, method="separable")
+    var = np.maximum(oracle.mean3d(v64 * v64, r, method="separable") - m * m, 0)
+    s = np.sqrt(var)
+    dvar = 4e-5 * (q_scale + m_scale * m_scale)
+    ds = np.where(s > np.sqrt(dvar), dvar / (2 * np.maximum(s, 1e-300)), np.sqrt(dvar))
+    if method == "niblack":
+        return dm + abs(k) * ds
+    return np.abs(1 + k * (s / R - 1)) * dm + np.abs(m * k / R) * ds
+
+
+@pytest.mark.parametrize("method,r,k", [("mean", 2, 0.0), ("gaussian", 0, 0.0), ("niblack", 2, -0.2),
+                                        ("sauvola", 3, 0.5), ("niblack", 6, 0.3), ("mean", 12, 0.0)])
+@pytest.mark.parametrize("dtype", ["f32", "u16", "u8"])
+def test_local_threshold(dev, method, r, k, dtype):
+    if dtype == "f32":
+        v = phantoms.porous(SHAPE, seed=106)
+    else:
+        v = phantoms.porous_u16(SHAPE, seed=106)
+        if dtype == "u8":
+            v = (v.to(torch.int32) >> 8).to(torch.uint8)
+    R = {"f32": 0.5, "u16": 32768.0, "u8": 128.0}[dtype]
+    c = {"f32": 0.01, "u16": 300.0, "u8": 1.0}[dtype] if method in ("mean", "gaussian") else 0.0
+    print("threshold", method, r, dtype, flush=True)
+    got = h.local_threshold(v.to(dev), method, radius=r, sigma=1.5, k=k, r_param=R, offset=c)
+    torch.cuda.synchronize()
+    assert got.dtype == torch.uint8
+    v64 = to_np64(v)
+    want, t = oracle.local_threshold3d(v64, method, radius=r, sigma=1.5, k=k, r_param=R, offset=c, return_t=True)
+    band = np.abs(v64 - t) <= _thr_band(v64, method, r, 1.5, k, R, c)
+    g = got.cpu().numpy()
+    bad = (g != want) & ~band
+    assert not bad.any(), "%d decisions differ outside the FP32 band" % int(bad.sum())
+    assert band.mean() < 0.02, band.mean()
+
+
+def test_local_threshold_chunked_and_limits(dev):
+    v = phantoms.porous_u16(SHAPE, seed=107)
+    res = h.local_threshold(v.to(dev), "sauvola", radius=2, k=0.3, r_param=32768.0)
+    chunked = h.local_threshold(v.to(dev), "sauvola", radius=2, k=0.3, r_param=32768.0,
+                                ex=h.Exec(force_chunked=True, chunk=(8, 16, 64), budget=64 << 20))
+    host = h.local_threshold(v.pin_memory(), "sauvola", radius=2, k=0.3, r_param=32768.0, ex=h.Exec(budget=8 << 20))
+    torch.cuda.synchronize()
+    assert torch.equal(chunked, res)
+    assert torch.equal(host, res.cpu())
+    x = torch.zeros((8, 9, 10), device=dev)
+    with pytest.raises(h.HarpiaError):
+        h.local_threshold(x, "niblack", radius=7)
+    with pytest.raises(h.HarpiaError):
+        h.local_threshold(x.to(torch.bfloat16), "mean", radius=1)
+    with pytest.raises(h.HarpiaError):
+        h.local_threshold(x, "sauvola", radius=1, r_param=0.0)
