@@ -356,6 +356,38 @@ def local_threshold3d(v, method: str, radius=1, sigma: float = 1.0, k: float = 0
     return (out, t) if return_t else out
 
 
+def otsu_threshold(v, nbins: int) -> int:
+    """Otsu's global threshold (Section III-C threshold algorithms) over the
+    integer histogram of v (one bin per value 0 .. nbins - 1): the split k
+    (class 0: values <= k) maximising the between-class variance
+    w0 w1 (m0 - m1)^2, w the class counts and m the class means, evaluated
+    in FP64 in this order from exact integer sums; the first maximum wins.
+    Returns -1 when every voxel holds one value."""
+    v = np.asarray(v).ravel().astype(np.int64)
+    counts = np.bincount(v, minlength=nbins)[:nbins].astype(np.int64)
+    n = int(counts.sum())
+    total = int(np.dot(np.arange(nbins, dtype=np.int64), counts))
+    best_k, best = -1, -1.0
+    c0 = s0 = 0
+    for k in range(nbins - 1):
+        c0 += int(counts[k])
+        s0 += k * int(counts[k])
+        c1 = n - c0
+        if c0 == 0 or c1 == 0:
+            continue
+        d = float(s0) / float(c0) - float(total - s0) / float(c1)
+        sb = (float(c0) * float(c1)) * (d * d)
+        if sb > best:
+            best, best_k = sb, k
+    return best_k
+
+
+def otsu3d(v, nbins: int) -> np.ndarray:
+    """uint8 (v > k) with k = otsu_threshold(v)."""
+    k = otsu_threshold(v, nbins)
+    return (np.asarray(v).astype(np.int64) > k).astype(np.uint8)
+
+
 def opening3d(v, se="box", radius=1):
     """Opening = dilation of the erosion, each over the full volume."""
     return dilate3d(erode3d(v, se, radius), se, radius)

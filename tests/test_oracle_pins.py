@@ -658,3 +658,35 @@ def test_local_threshold_closed_forms():
     w[0] = 27.0  # one face of 9 voxels at 27, the rest 0: m = 9, s = sqrt(243 - 81)
     _, t = oracle.local_threshold3d(w, "niblack", 1, k=1.0, return_t=True)
     assert abs(t[1, 1, 1] - (9.0 + math.sqrt(162.0))) < 1e-12
+
+
+# -------------------------------------------------------------------- Otsu
+
+def test_otsu_minimises_within_class_variance_brute_force():
+    # Otsu's split maximises the between-class variance, which is the same as
+    # minimising the within-class variance computed from the values directly
+    rng = _rng(100)
+    v = np.concatenate([rng.normal(60, 8, 3000), rng.normal(170, 15, 2000)]).clip(0, 255).astype(np.int64)
+    k = oracle.otsu_threshold(v, 256)
+    best_k, best = None, None
+    for t in range(255):
+        a, b = v[v <= t], v[v > t]
+        if len(a) == 0 or len(b) == 0:
+            continue
+        w = len(a) * a.var() + len(b) * b.var()
+        if best is None or w < best - 1e-9 * abs(best):
+            best, best_k = w, t
+    # ties in the within-class form may pick a neighbouring empty bin: the
+    # two splits must put every voxel in the same class
+    assert np.array_equal(v > k, v > best_k)
+
+
+def test_otsu_hand_worked():
+    # two values: every split between them is optimal; the first one wins
+    v = np.array([3, 3, 3, 10, 10])
+    assert oracle.otsu_threshold(v, 16) == 3
+    np.testing.assert_array_equal(oracle.otsu3d(v, 16), [0, 0, 0, 1, 1])
+    assert oracle.otsu_threshold(np.full(7, 5), 16) == -1
+    # three equal clusters at 0, 10, 20: the variance of a split {0} | {10, 20}
+    # (1 * 2 * (0 - 15)^2 = 450 per triple) equals {0, 10} | {20}: first wins
+    assert oracle.otsu_threshold(np.repeat([0, 10, 20], 4), 32) == 0
