@@ -473,6 +473,7 @@ def run_filters(args):
     out = torch.empty_like(v)
     hout = torch.empty((6,) + tuple(v.shape), dtype=torch.float32, device=dev)
     bout = torch.empty(tuple(v.shape), dtype=torch.uint8, device=dev)
+    v16 = phantoms.porous_u16((n, n, n), seed=0, device=dev)
     if args.tune:
         # the mean filter runs the fused kernel of radius r (sigma 0.34 and
         # 0.5 resolve to r = 1 and 2: same kernel, same workload key)
@@ -484,7 +485,8 @@ def run_filters(args):
     ops = [("mean_r1", lambda: h.mean(v, 1, out=out)), ("mean_r2", lambda: h.mean(v, 2, out=out)),
            ("unsharp_s2_a1", lambda: h.unsharp(v, 2.0, 1.0, out=out)), ("sobel", lambda: h.edge(v, "sobel", out=out)),
            ("hessian_s1_6out", lambda: h.hessian(v, 1.0, out=hout)),
-           ("niblack_r2", lambda: h.local_threshold(v, "niblack", radius=2, k=-0.2, out=bout))]
+           ("niblack_r2", lambda: h.local_threshold(v, "niblack", radius=2, k=-0.2, out=bout)),
+           ("otsu_u16", lambda: h.otsu(v16, out=bout))]
     for _ in range(args.warmup):
         for _, fn in ops:
             fn()
@@ -506,7 +508,9 @@ def run_filters(args):
         # algorithmic bytes: read once, write once (the unsharp epilogue's
         # read of the centre voxel is a re-read); the Hessian writes 6 outputs
         nout = 6 if name.startswith("hessian") else 1
-        alg = (4 + 4 * nout) if not name.startswith("niblack") else 5  # the threshold writes a byte
+        # thresholds write a byte; Otsu reads the u16 volume twice (histogram,
+        # then the comparison) and writes a byte
+        alg = {"niblack_r2": 5, "otsu_u16": 5}.get(name, 4 + 4 * nout)
         per_op[name] = {"ms": round(ms, 4), "gvox_s": round(nout * vox / ms / 1e6, 2),
                         "hbm_frac": round(alg * vox / ms / 1e6 / HBM_PEAK_GBS, 4)}
     ms_step = wall * 1000 / args.steps
@@ -521,7 +525,8 @@ def run_filters(args):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": "filters: %d^3 float32 porous phantom, mean r=1,2 + unsharp sigma 2 amount 1 + "
-                                   "Sobel magnitude + Hessian sigma 1 (6 outputs) + Niblack r=2" % n,
+                                   "Sobel magnitude + Hessian sigma 1 (6 outputs) + Niblack r=2 + Otsu (uint16 "
+                                   "phantom)" % n,
                        "voxels": vox},
             "roofline": roof, "ops": per_op, "tiles": tiles}
     if not args.no_cpu:

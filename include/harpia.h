@@ -232,6 +232,19 @@ harpia_status harpia_local_threshold3d(const void *in, harpia_dtype t,
                                        harpia_border border,
                                        const harpia_exec *ex);
 
+/* Otsu's global threshold (Section III-C, threshold algorithms) of an
+ * integer volume, one histogram bin per value (U8: 256 bins, U16: 65536):
+ * k = the split (class 0: values <= k) maximising w0 w1 (m0 - m1)^2, the
+ * class counts w and means m, evaluated in FP64 from exact integer sums;
+ * the first maximum wins; k = -1 when the volume holds one value.
+ * out (device, may be NULL) receives (in > k) as uint8; threshold (host or
+ * device pointer, may be NULL) receives k.  Device-resident volumes only
+ * (else UNSUPPORTED); synchronises ex->stream before returning.
+ * Errors: ARG, DTYPE, ALIAS, OOM, HIP, UNSUPPORTED. */
+harpia_status harpia_otsu3d(const void *in, harpia_dtype t, uint8_t *out,
+                            const int64_t shape[3], int64_t *threshold,
+                            const harpia_exec *ex);
+
 /* Sobel / Prewitt edge enhancement (Section III-C, filtering suite):
  *   G_a = central difference [-1, 0, 1] (in[i+1] - in[i-1]) along axis a,
  *         smoothed by [1, 2, 1] (HARPIA_EDGE_SOBEL) or [1, 1, 1]

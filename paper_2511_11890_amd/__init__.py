@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import HarpiaError, harpia_plan, harpia_stats
 
-__all__ = ["gaussian", "mean", "unsharp", "edge", "hessian", "local_threshold", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
+__all__ = ["gaussian", "mean", "unsharp", "edge", "hessian", "local_threshold", "otsu", "erode", "dilate", "erode_dilate", "opening", "closing", "morph",
            "plan", "gauss_radius", "version", "HarpiaError", "harpia_stats", "Exec",
            "gaussian_backward", "morph_backward", "GaussianFn", "MorphFn", "GaussDilateFn",
            "gaussian_batched", "morph_batched", "GaussDilateBatch", "autotune_gaussian",
@@ -229,6 +229,21 @@ def local_threshold(x, method: str = "mean", radius: int = 1, sigma: float = 1.0
             {"mean": 0, "gaussian": 1, "niblack": 2, "sauvola": 3}[method], int(radius), float(sigma),
             float(truncate), float(k), float(r_param), float(offset), _lib.HARPIA_BORDER_REFLECT, e))
     return out
+
+
+def otsu(x, out=None, binarize: bool = True, ex: Exec | None = None):
+    """Otsu's global threshold of a device-resident u8 / u16 volume: returns
+    (uint8 (x > k) or None, k)."""
+    _check_volume(x)
+    ic = _dtype_code(x)
+    if binarize and out is None:
+        out = _empty_like(x, _lib.HARPIA_U8)
+    k = _ctypes.c_int64(0)
+    e = _exec(x, ex)
+    with _device_guard(x):
+        _lib.check(_lib.load().harpia_otsu3d(_ptr(x), ic, _ptr(out) if binarize else None, _lib.i64_3(x.shape),
+                                             _ctypes.byref(k), e))
+    return (out if binarize else None), int(k.value)
 
 
 def hessian(x, sigma, truncate: float = 3.0, out=None, ex: Exec | None = None):

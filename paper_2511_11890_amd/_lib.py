@@ -98,6 +98,7 @@ SIGNATURES = {
     "harpia_gaussian3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _I64_3, _F64_3,
                                          ctypes.c_double, ctypes.c_int, _ex]),
     "harpia_mean3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _I64_3, _I32_3, ctypes.c_int, _ex]),
+    "harpia_otsu3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _I64_3, ctypes.POINTER(ctypes.c_int64), _ex]),
     "harpia_local_threshold3d": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _I64_3, ctypes.c_int, ctypes.c_int32,
                                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                 ctypes.c_double, ctypes.c_int, _ex]),

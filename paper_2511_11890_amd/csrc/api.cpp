@@ -292,6 +292,33 @@ harpia_status harpia_mean3d(const void *in, harpia_dtype in_t, void *out, harpia
     });
 }
 
+harpia_status harpia_otsu3d(const void *in, harpia_dtype t, uint8_t *out, const int64_t shape[3],
+                            int64_t *threshold, const harpia_exec *ex)
+{
+    return guarded([&] {
+        if (!in) fail(HARPIA_ERR_ARG, "in is NULL");
+        check_shape(shape);
+        check_exec(ex);
+        if (t != HARPIA_U8 && t != HARPIA_U16) fail(HARPIA_ERR_DTYPE, "Otsu's threshold takes u8 or u16 volumes");
+        const int64_t nv = voxels(shape);
+        if (out) check_alias(in, nv * dtype_size(t), out, nv);
+        if (!is_device_pointer(in) || (out && !is_device_pointer(out)))
+            fail(HARPIA_ERR_UNSUPPORTED, "Otsu's threshold runs on device-resident volumes");
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        DevBuf hist, res;
+        const int nb = otsu_bins(t);
+        hist.alloc((size_t)nb * sizeof(unsigned long long));
+        res.alloc(sizeof(int64_t));
+        check_hip(hipMemsetAsync(hist.p, 0, (size_t)nb * sizeof(unsigned long long), s), "hipMemsetAsync");
+        if (!launch_otsu(in, t, nv, out, static_cast<unsigned long long *>(hist.p), static_cast<int64_t *>(res.p), s))
+            fail(HARPIA_ERR_DTYPE, "no Otsu kernel for this dtype");
+        check_hip(hipGetLastError(), "kernel launch");
+        if (threshold)
+            check_hip(hipMemcpyAsync(threshold, res.p, sizeof(int64_t), hipMemcpyDefault, s), "hipMemcpyAsync");
+        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    });
+}
+
 harpia_status harpia_local_threshold3d(const void *in, harpia_dtype t, uint8_t *out, const int64_t shape[3],
                                        harpia_threshold_method method, int32_t radius, double sigma, double truncate,
                                        double k, double r_param, double offset, harpia_border border,

@@ -249,6 +249,12 @@ int64_t gauss_sigma3_blocks_bound(const int64_t n[3]);
 bool launch_gaussian(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t,
                      const GaussTaps &taps, hipStream_t s, void *scratch,
                      size_t scratch_bytes);
+// Otsu's threshold of a device volume (u8 / u16): hist (otsu_bins(t)
+// 64-bit counters, zeroed by the caller) and result (1 int64) are device
+// scratch; out (may be NULL) receives v > k.  Returns false for other dtypes.
+int otsu_bins(harpia_dtype t);
+bool launch_otsu(const void *v, harpia_dtype t, int64_t n, uint8_t *out, unsigned long long *hist, int64_t *result,
+                 hipStream_t s);
 // Local threshold of one chunk (uint8 out); taps hold the box or Gaussian
 // weights.  Returns false for unsupported dtypes / radii.
 bool launch_local_threshold(const ChunkArgs &a, harpia_dtype in_t, const GaussTaps &taps, int method, float k,

@@ -307,3 +307,38 @@ def test_local_threshold_chunked_and_limits(dev):
         h.local_threshold(x.to(torch.bfloat16), "mean", radius=1)
     with pytest.raises(h.HarpiaError):
         h.local_threshold(x, "sauvola", radius=1, r_param=0.0)
+
+
+# -------------------------------------------------------------------- Otsu
+# The split is decided in FP64 from exact integer sums on both sides: the
+# threshold and the binary volume must equal the oracle's exactly.
+
+@pytest.mark.parametrize("dtype", ["u8", "u16"])
+@pytest.mark.parametrize("shape", [SHAPE, (1, 1, 777), (64, 64, 64)])
+def test_otsu(dev, dtype, shape):
+    v = phantoms.porous_u16(shape, seed=108)
+    nb = 65536
+    if dtype == "u8":
+        v = (v.to(torch.int32) >> 8).to(torch.uint8)
+        nb = 256
+    print("otsu", dtype, shape, flush=True)
+    out, k = h.otsu(v.to(dev))
+    torch.cuda.synchronize()
+    v64 = v.to(torch.int64).numpy()
+    assert k == oracle.otsu_threshold(v64, nb)
+    np.testing.assert_array_equal(out.cpu().numpy(), oracle.otsu3d(v64, nb))
+
+
+def test_otsu_degenerate(dev):
+    c = torch.full((5, 6, 7), 9, dtype=torch.uint8, device=dev)
+    out, k = h.otsu(c)
+    torch.cuda.synchronize()
+    assert k == -1 and bool(out.all())
+    two = torch.tensor([3, 3, 3, 10, 10], dtype=torch.uint8, device=dev).reshape(1, 1, 5)
+    out, k = h.otsu(two)
+    torch.cuda.synchronize()
+    assert k == 3 and out.cpu().flatten().tolist() == [0, 0, 0, 1, 1]
+    none, k2 = h.otsu(two, binarize=False)
+    assert none is None and k2 == 3
+    with pytest.raises(h.HarpiaError):
+        h.otsu(torch.zeros((4, 4, 4), device=dev))  # float32: not an integer volume
