@@ -547,7 +547,7 @@ harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t, const 
             GaussTaps taps;
             make_gauss_taps_r(sigma, r, taps);
             const ChunkArgs a = make_chunk_args(g_reg, whole_region(grad_in, shape), shape);
-            const size_t need = gaussian_scratch_bytes(shape, r);
+            const size_t need = gaussian_scratch_bytes(shape, r, gauss_slices_fit(shape));
             if (need) {
                 scratch.alloc(need);
                 allocated = true;
@@ -585,27 +585,19 @@ harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t, const 
             for (int axis = 0; axis < 3 && !one_pass; ++axis) {
                 GaussTaps dt;
                 make_gauss_dtaps_r(sigma, r, axis, dt);
-                const ChunkArgs a = make_chunk_args(x_reg, g_reg, shape);
-                int64_t nb;
-                if (gauss_fused_ok(dt, a)) {
-                    if (!partials.p) partials.alloc((size_t)gauss_dot_blocks(a, dt) * sizeof(float));
-                    nb = launch_gauss_dot(a, x_t, dt, s, static_cast<float *>(partials.p));
-                    if (nb < 0) fail(HARPIA_ERR_UNSUPPORTED, "no fused kernel for these radii");
-                } else {
-                    // unfused: the derivative volume, then its dot with g
-                    if (!dvol.p) {
-                        dvol.alloc((size_t)nv * sizeof(float));
-                        const size_t need = gaussian_scratch_bytes(shape, r);
-                        if (need && !scratch.p) scratch.alloc(need);
-                    }
-                    const Region d_reg = whole_region(dvol.p, shape);
-                    const ChunkArgs ad = make_chunk_args(x_reg, d_reg, shape);
-                    if (!launch_gaussian(ad, x_t, HARPIA_F32, dt, s, scratch.p, gaussian_scratch_bytes(shape, r)))
-                        fail(HARPIA_ERR_UNSUPPORTED, "no Gaussian kernel for these radii");
-                    const int64_t max_blocks = 4096;
-                    if (!partials.p) partials.alloc((size_t)max_blocks * sizeof(float));
-                    nb = launch_dot_partials(d_reg, g_reg, static_cast<float *>(partials.p), max_blocks, s);
+                // unfused: the derivative volume, then its dot with g
+                if (!dvol.p) {
+                    dvol.alloc((size_t)nv * sizeof(float));
+                    const size_t need = gaussian_scratch_bytes(shape, r, false);
+                    if (need && !scratch.p) scratch.alloc(need);
                 }
+                const Region d_reg = whole_region(dvol.p, shape);
+                const ChunkArgs ad = make_chunk_args(x_reg, d_reg, shape);
+                if (!launch_gaussian(ad, x_t, HARPIA_F32, dt, s, scratch.p, gaussian_scratch_bytes(shape, r, false)))
+                    fail(HARPIA_ERR_UNSUPPORTED, "no Gaussian kernel for these radii");
+                const int64_t max_blocks = 4096;
+                if (!partials.p) partials.alloc((size_t)max_blocks * sizeof(float));
+                const int64_t nb = launch_dot_partials(d_reg, g_reg, static_cast<float *>(partials.p), max_blocks, s);
                 check_hip(hipGetLastError(), "kernel launch");
                 launch_reduce_f64(static_cast<const float *>(partials.p), nb, dst + axis, false, s);
                 check_hip(hipGetLastError(), "kernel launch");

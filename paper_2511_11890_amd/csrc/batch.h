@@ -75,10 +75,6 @@ inline int64_t batch_grid(int64_t items, int64_t capacity) { return items < capa
 // Batched launches (see api.cpp for the C entry points).
 bool launch_gauss_batched(const BatchDesc &d, harpia_dtype in_t, harpia_dtype out_t, const GaussTaps &taps,
                           hipStream_t s);
-// Per-block partials of sum g * (G x) over the batch (in = x, out = g);
-// returns the partial count, or -1.
-int64_t launch_gauss_dot_batched(const BatchDesc &d, harpia_dtype in_t, const GaussTaps &taps, hipStream_t s,
-                                 float *partials);
 int64_t gauss_batched_max_partials();
 // The three sigma-gradient terms over a batch in one pass (in = x, out =
 // upstream gradient): partials[a grid + b]; returns grid, or -1.

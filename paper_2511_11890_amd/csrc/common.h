@@ -268,6 +268,9 @@ bool launch_edge(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t, int 
 // fused = false: the bytes of the unfused passes even where a fused kernel
 // exists (odd taps are fused for float32 -> float32 only).
 size_t gaussian_scratch_bytes(const int64_t out_e[3], const int r[3], bool fused = true);
+// The fused Gaussian addresses a slice of the input with 32-bit offsets: a
+// volume of extent n whose slices are too large takes the unfused passes.
+inline bool gauss_slices_fit(const int64_t n[3]) { return n[2] * (n[1] + 1) < ((int64_t)1 << 31); }
 
 struct MorphSpec {
     int op;              // 0 erode (min), 1 dilate (max)
@@ -287,14 +290,6 @@ float compare_threshold(harpia_dtype t, double thr);
 
 // ---------------------------------------------------------- adjoints
 
-// Per-block partials of sum g * (G x) (g = a.out, float, output-region
-// layout) with the fused kernel; returns the partial count or -1 if the
-// taps / dtype need the unfused path.
-int64_t launch_gauss_dot(const ChunkArgs &a, harpia_dtype in_t, const GaussTaps &taps, hipStream_t s,
-                         float *partials);
-// Upper bound of the partials launch_gauss_dot writes.
-int64_t gauss_dot_blocks(const ChunkArgs &a, const GaussTaps &taps);
-bool gauss_fused_ok(const GaussTaps &taps, const ChunkArgs &a);
 // sum of partials[0..n) in FP64, fixed order, into out[0] (or added to it).
 void launch_reduce_f64(const float *partials, int64_t n, double *out, bool accumulate, hipStream_t s);
 // Per-block partials of sum a * b over a region; returns the block count.

@@ -164,10 +164,10 @@ Region volume_region(const void *base, size_t es, const int64_t n[3], const int6
     return r;
 }
 
-size_t stage_scratch(const Stage &st, const int64_t ext[3])
+size_t stage_scratch(const Stage &st, const int64_t ext[3], const int64_t n[3])
 {
     if (st.kind != Stage::GAUSS) return 0;
-    const bool fused = !st.taps.odd || (st.in_t == HARPIA_F32 && st.out_t == HARPIA_F32);
+    const bool fused = gauss_slices_fit(n) && (!st.taps.odd || (st.in_t == HARPIA_F32 && st.out_t == HARPIA_F32));
     return gaussian_scratch_bytes(ext, st.r, fused);
 }
 
@@ -224,7 +224,7 @@ void chunk_layout(const std::vector<Stage> &st, const int64_t c0[3], const int64
         expand(c0, c1, h, n, lo, hi);
         for (int a = 0; a < 3; ++a) ext[a] = hi[a] - lo[a];
         if (k + 1 < st.size()) inter_bytes[k] = align_up((size_t)vol(ext) * dtype_size(st[k].out_t));
-        scratch = std::max(scratch, align_up(stage_scratch(st[k], ext)));
+        scratch = std::max(scratch, align_up(stage_scratch(st[k], ext, n)));
     }
 }
 
@@ -240,7 +240,7 @@ void worst_layout(const std::vector<Stage> &st, const int64_t core[3], const int
         tail_halo(st, k, h);
         for (int a = 0; a < 3; ++a) ext[a] = std::min(n[a], std::min(core[a], n[a]) + 2 * h[a]);
         if (k + 1 < st.size()) inter_bytes[k] = align_up((size_t)vol(ext) * dtype_size(st[k].out_t));
-        scratch = std::max(scratch, align_up(stage_scratch(st[k], ext)));
+        scratch = std::max(scratch, align_up(stage_scratch(st[k], ext, n)));
     }
 }
 

@@ -33,12 +33,8 @@ namespace harpia {
 
 template <typename Tin, typename Tout>
 bool gauss_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes);
-template <typename Tin>
-int64_t gauss_dot_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials);
 template <typename Tin, typename Tout>
 bool gauss_batched_run(const BatchDesc &d, const GaussTaps &taps, hipStream_t s);
-template <typename Tin>
-int64_t gauss_dot_batched_run(const BatchDesc &d, const GaussTaps &taps, hipStream_t s, float *partials);
 template <typename Tin>
 int64_t gauss_sigma3_run(const Tin *x, const float *g, const int64_t n[3], const GaussTaps &wt, const GaussTaps &dt,
                          hipStream_t s, float *partials);
@@ -89,13 +85,6 @@ bool launch_gauss_batched(const BatchDesc &d, harpia_dtype in_t, harpia_dtype ou
 {
     if (in_t != HARPIA_F32 || out_t != HARPIA_F32) return false;
     return gauss_batched_run<float, float>(d, taps, s);
-}
-
-int64_t launch_gauss_dot_batched(const BatchDesc &d, harpia_dtype in_t, const GaussTaps &taps, hipStream_t s,
-                                 float *partials)
-{
-    if (in_t != HARPIA_F32) return -1;
-    return gauss_dot_batched_run<float>(d, taps, s, partials);
 }
 
 int64_t gauss_batched_max_partials() { return 8192; }
@@ -187,27 +176,6 @@ void make_gauss_taps(const double sigma[3], double truncate, GaussTaps &t)
     int r[3];
     for (int ax = 0; ax < 3; ++ax) r[ax] = (int)(truncate * sigma[ax] + 0.5);
     make_gauss_taps_r(sigma, r, t);
-}
-
-bool gauss_fused_ok(const GaussTaps &taps, const ChunkArgs &a) { return gauss_detail::fused_ok(taps, a); }
-
-int64_t gauss_dot_blocks(const ChunkArgs &a, const GaussTaps &taps)
-{
-    (void)taps;
-    return gauss_detail::fused_blocks_bound(a);
-}
-
-int64_t launch_gauss_dot(const ChunkArgs &a, harpia_dtype in_t, const GaussTaps &taps, hipStream_t s,
-                         float *partials)
-{
-    switch (in_t) {
-    case HARPIA_F32: return gauss_dot_run<float>(a, taps, s, partials);
-    case HARPIA_U16: return gauss_dot_run<uint16_t>(a, taps, s, partials);
-    case HARPIA_U8: return gauss_dot_run<uint8_t>(a, taps, s, partials);
-    case HARPIA_F16: return gauss_dot_run<_Float16>(a, taps, s, partials);
-    case HARPIA_BF16: return gauss_dot_run<bf16_t>(a, taps, s, partials);
-    }
-    return -1;
 }
 
 bool launch_gaussian(const ChunkArgs &a, harpia_dtype in_t, harpia_dtype out_t, const GaussTaps &taps,

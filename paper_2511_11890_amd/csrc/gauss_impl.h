@@ -125,21 +125,6 @@ struct StoreOut {
     }
 };
 
-// Accumulates sum over outputs of g[o] * filtered[o] (g laid out like the
-// output region): with derivative taps on one axis this is one term of the
-// sigma-gradient.
-struct DotOut {
-    const float *g;
-    float sum;
-    __device__ __forceinline__ void prefetch(int64_t, int) {}
-    __device__ __forceinline__ void put(int64_t off, int64_t, int nvalid, const float v[4])
-    {
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (c < nvalid) sum = fmaf(g[off + c], v[c], sum);
-    }
-};
-
 // One tile of the fused Gaussian: output columns [x0, x0 + kTX) x
 // [y0, y0 + kTY) of the output region, slices [zo0, zo0 + zlen).
 // PAR: bit a set (z = 1, y = 2, x = 4) when the taps of axis a are odd,
@@ -607,22 +592,6 @@ __global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps
     gauss_tile<Tin, R, D, StoreOut<Tin, Tout, UNSHARP>, PAR>(a, taps, zlen, bx, by, bz, out);
 }
 
-
-// sigma-gradient term: per-block FP32 partial of sum g * (G' x); a.out is
-// the upstream gradient g (float, laid out like the output region).
-template <typename Tin, int R, int D = gauss_prefetch_depth(R)>
-__global__ __launch_bounds__(kNT) void gauss_dot_kernel(ChunkArgs a, GaussTaps taps, int zlen, int tiles_x,
-                                                        int tiles_y, float *partials)
-{
-    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-    int bx, by, bz;
-    tile_of_block(b, tiles_x, tiles_y, bx, by, bz);
-    DotOut out{static_cast<const float *>(a.out), 0.f};
-    gauss_tile<Tin, R, D>(a, taps, zlen, bx, by, bz, out);
-    const float t = block_sum_256(out.sum);
-    if (threadIdx.x == 0) partials[b] = t;
-}
-
 // Persistent batched Gaussian: workgroup b takes work items
 // xcd_remap(b) + k * gridDim (so the workgroups of one XCD hold neighbouring
 // tiles at any time); the LDS of the tile routine is reused between items.
@@ -638,25 +607,6 @@ __global__ __launch_bounds__(kNT) void gauss_batched_kernel(BatchDesc d, GaussTa
         gauss_tile<Tin, R, D>(a, taps, d.c[c].zlen, bx, by, bz, out);
         lds_barrier();
     }
-}
-
-// Batched sigma-gradient term: one FP32 partial per workgroup over all of
-// its items (in = x, out = upstream gradient).
-template <typename Tin, int R, int D = gauss_prefetch_depth(R)>
-__global__ __launch_bounds__(kNT) void gauss_dot_batched_kernel(BatchDesc d, GaussTaps taps, float *partials)
-{
-    const int total = d.prefix[d.n_crops];
-    DotOut out{nullptr, 0.f};
-    for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
-        int c, bx, by, bz;
-        batch_item(d, w, c, bx, by, bz);
-        const ChunkArgs a = crop_args(d.c[c]);
-        out.g = static_cast<const float *>(a.out);
-        gauss_tile<Tin, R, D>(a, taps, d.c[c].zlen, bx, by, bz, out);
-        lds_barrier();
-    }
-    const float t = block_sum_256(out.sum);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
 // One 1D pass along `axis` (0 z, 1 y, 2 x): dst = w * src, reflect along the
@@ -722,44 +672,6 @@ bool launch_fused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
     if (taps.odd) return false;
     launch_fused_u<Tin, Tout, R, false>(a, taps, s);
     return true;
-}
-
-template <typename Tin, int R>
-int64_t launch_dot(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
-{
-    static const int64_t cap = resident_blocks(gauss_dot_kernel<Tin, R>, kNT);
-    Tile t;
-    const bool tuned =
-        tune_lookup(TF_GAUSS_DOT, tune_key_volume(TF_GAUSS_DOT, R, tune_type_code<Tin>(), a.out_e), t);
-    const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0);
-    hipLaunchKernelGGL((gauss_dot_kernel<Tin, R>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, taps, g.zlen,
-                       g.tiles_x, g.tiles_y, partials);
-    return g.blocks;
-}
-
-template <typename Tin>
-int64_t dispatch_dot(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
-{
-    switch (r) {
-#define HARPIA_CASE(RR) \
-    case RR:            \
-        return launch_dot<Tin, RR>(a, taps, s, partials);
-        HARPIA_CASE(1)
-        HARPIA_CASE(2)
-        HARPIA_CASE(3)
-        HARPIA_CASE(4)
-        HARPIA_CASE(5)
-        HARPIA_CASE(6)
-        HARPIA_CASE(7)
-        HARPIA_CASE(8)
-        HARPIA_CASE(9)
-        HARPIA_CASE(10)
-        HARPIA_CASE(11)
-        HARPIA_CASE(12)
-#undef HARPIA_CASE
-    default:
-        return false;
-    }
 }
 
 template <typename Tin, typename Tout>
@@ -858,21 +770,6 @@ void launch_batched(BatchDesc d, const GaussTaps &taps, hipStream_t s)
         hipLaunchKernelGGL((gauss_batched_kernel<Tin, Tout, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, taps);
 }
 
-template <typename Tin, int R>
-int64_t launch_dot_batched(BatchDesc d, const GaussTaps &taps, hipStream_t s, float *partials)
-{
-    static const int64_t cap = resident_blocks(gauss_dot_batched_kernel<Tin, R>, kNT);
-    Tile t;
-    const bool tuned =
-        tune_lookup(TF_GAUSS_DOT_BATCHED, tune_key_batch(TF_GAUSS_DOT_BATCHED, R, tune_type_code<Tin>(), d), t);
-    batch_layout(d, kTX, kTY, tuned && t.tz > 0 ? t.tz : kBatchZ);
-    const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < kBatchMaxGrid ? cap : kBatchMaxGrid);
-    if (grid > 0)
-        hipLaunchKernelGGL((gauss_dot_batched_kernel<Tin, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, taps,
-                           partials);
-    return grid;
-}
-
 template <typename Tin, typename Tout>
 bool dispatch_batched(int r, const BatchDesc &d, const GaussTaps &taps, hipStream_t s)
 {
@@ -896,31 +793,6 @@ bool dispatch_batched(int r, const BatchDesc &d, const GaussTaps &taps, hipStrea
 #undef HARPIA_CASE
     default:
         return false;
-    }
-}
-
-template <typename Tin>
-int64_t dispatch_dot_batched(int r, const BatchDesc &d, const GaussTaps &taps, hipStream_t s, float *partials)
-{
-    switch (r) {
-#define HARPIA_CASE(RR) \
-    case RR:            \
-        return launch_dot_batched<Tin, RR>(d, taps, s, partials);
-        HARPIA_CASE(1)
-        HARPIA_CASE(2)
-        HARPIA_CASE(3)
-        HARPIA_CASE(4)
-        HARPIA_CASE(5)
-        HARPIA_CASE(6)
-        HARPIA_CASE(7)
-        HARPIA_CASE(8)
-        HARPIA_CASE(9)
-        HARPIA_CASE(10)
-        HARPIA_CASE(11)
-        HARPIA_CASE(12)
-#undef HARPIA_CASE
-    default:
-        return -1;
     }
 }
 
@@ -1039,26 +911,10 @@ int64_t gauss_sigma3_batched_run(const BatchDesc &d, const GaussTaps &wt, const 
     }
 }
 
-template <typename Tin>
-int64_t gauss_dot_batched_run(const BatchDesc &d, const GaussTaps &taps, hipStream_t s, float *partials)
-{
-    if (!(taps.r[0] == taps.r[1] && taps.r[1] == taps.r[2])) return -1;
-    return gauss_detail::dispatch_dot_batched<Tin>(taps.r[0], d, taps, s, partials);
-}
-
 template <typename Tin, typename Tout>
 bool gauss_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, void *scratch, size_t scratch_bytes)
 {
     return gauss_detail::run<Tin, Tout>(a, taps, s, scratch, scratch_bytes);
-}
-
-// Per-block partials of sum g * (G x) for the fused case (equal radii
-// 1..kGaussFusedMaxR).  Returns the number of partials written, or -1.
-template <typename Tin>
-int64_t gauss_dot_run(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s, float *partials)
-{
-    if (!gauss_detail::fused_ok(taps, a)) return -1;
-    return gauss_detail::dispatch_dot<Tin>(taps.r[0], a, taps, s, partials);
 }
 
 }  // namespace harpia
