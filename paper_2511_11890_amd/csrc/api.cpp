@@ -300,6 +300,7 @@ harpia_status harpia_otsu3d(const void *in, harpia_dtype t, uint8_t *out, const 
         check_shape(shape);
         check_exec(ex);
         if (t != HARPIA_U8 && t != HARPIA_U16) fail(HARPIA_ERR_DTYPE, "Otsu's threshold takes u8 or u16 volumes");
+        if (t == HARPIA_U16 && (reinterpret_cast<uintptr_t>(in) & 1)) fail(HARPIA_ERR_ARG, "u16 volume not 2-byte aligned");
         const int64_t nv = voxels(shape);
         if (out) check_alias(in, nv * dtype_size(t), out, nv);
         if (!is_device_pointer(in) || (out && !is_device_pointer(out)))

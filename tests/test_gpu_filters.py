@@ -329,6 +329,28 @@ def test_otsu(dev, dtype, shape):
     np.testing.assert_array_equal(out.cpu().numpy(), oracle.otsu3d(v64, nb))
 
 
+@pytest.mark.parametrize("dtype", ["u8", "u16"])
+def test_otsu_unaligned_and_large(dev, dtype):
+    # a view that starts 3 elements into its storage (unaligned head and tail,
+    # element-wise binarisation), and a 128^3 volume (many segments, the
+    # concentrated two-phase histogram)
+    nb = 256 if dtype == "u8" else 65536
+    for shape, off in [((13, 17, 61), 3), ((128, 128, 128), 0)]:
+        n = int(np.prod(shape))
+        flat = phantoms.porous_u16((1, 1, n + off), seed=109).flatten()
+        if dtype == "u8":
+            flat = (flat.to(torch.int32) >> 8).to(torch.uint8)
+        g = flat.to(dev)
+        v = g[off:off + n].view(shape)
+        assert off == 0 or v.data_ptr() % 16 != 0
+        print("otsu", dtype, shape, off, flush=True)
+        out, k = h.otsu(v)
+        torch.cuda.synchronize()
+        v64 = flat[off:off + n].view(shape).to(torch.int64).numpy()
+        assert k == oracle.otsu_threshold(v64, nb)
+        np.testing.assert_array_equal(out.cpu().numpy(), oracle.otsu3d(v64, nb))
+
+
 def test_otsu_degenerate(dev):
     c = torch.full((5, 6, 7), 9, dtype=torch.uint8, device=dev)
     out, k = h.otsu(c)
