@@ -15,7 +15,8 @@ import torch
 import oracle
 import paper_2511_11890_amd as h
 from paper_2511_11890_amd import phantoms
-from tests.gpu_util import FP32_GAUSS_TOL, U_BF16, U_F16, assert_gauss_close, gauss_scale, to_np64
+from tests.gpu_util import (FP32_GAUSS_TOL, U_BF16, U_F16, assert_gauss_close, gauss_scale, sample_points, to_np64,
+                            window_of)
 
 pytestmark = pytest.mark.gpu
 
@@ -364,3 +365,78 @@ def test_otsu_degenerate(dev):
     assert none is None and k2 == 3
     with pytest.raises(h.HarpiaError):
         h.otsu(torch.zeros((4, 4, 4), device=dev))  # float32: not an integer volume
+
+
+# ------------------------------------------------- full size (1024^3, the
+# filters workload's shapes and launch configuration): sampled voxels, each
+# against the oracle on its reflected neighbourhood.
+
+@pytest.fixture(scope="module")
+def big_f32(dev):
+    return phantoms.porous((1024, 1024, 1024), seed=0, device=dev)
+
+
+def _sampled(got, pts, dev):
+    idx = torch.tensor(pts, device=dev)
+    if got.dim() == 4:
+        return got[:, idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy().T
+    return got[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+
+
+@pytest.mark.parametrize("op", ["mean_r1", "mean_r2", "unsharp_s2", "sobel", "hessian_s1", "niblack_r2"])
+def test_filters_full_size_sampled(dev, big_f32, op):
+    v = big_f32
+    shape = tuple(v.shape)
+    print("full-size", op, flush=True)
+    if op.startswith("mean"):
+        r = int(op[-1])
+        got = h.mean(v, r)
+    elif op == "unsharp_s2":
+        r = oracle.gauss_radius(2.0)
+        got = h.unsharp(v, 2.0, 1.0)
+    elif op == "sobel":
+        r = 1
+        got = h.edge(v, "sobel")
+    elif op == "hessian_s1":
+        r = oracle.gauss_radius(1.0)
+        got = h.hessian(v, 1.0)
+    else:
+        r = 2
+        got = h.local_threshold(v, "niblack", radius=2, k=-0.2)
+    torch.cuda.synchronize()
+    pts = sample_points(shape, 48, seed=len(op))
+    gvals = _sampled(got, pts, dev)
+    del got
+    for p, g in zip(pts, gvals):
+        win = window_of(v, p, r)
+        c = (r, r, r)
+        if op.startswith("mean"):
+            want, scale = oracle.mean3d(win, r, method="direct")[c], _mean_scale(win, r)[c]
+        elif op == "unsharp_s2":
+            want, scale = oracle.unsharp3d(win, 2.0, 1.0)[c], _unsharp_scale(win, 2.0, 1.0)[c]
+        elif op == "sobel":
+            want, scale = oracle.edge3d(win, "sobel")[c], _edge_scale(win, "sobel")[c]
+        elif op == "hessian_s1":
+            want = oracle.hessian3d(win, 1.0)[(slice(None),) + c]
+            scale = _hess_scale(win, 1.0)[(slice(None),) + c]
+        else:
+            out, t = oracle.local_threshold3d(win, "niblack", radius=2, k=-0.2, return_t=True)
+            if abs(win[c] - t[c]) > _thr_band(win, "niblack", 2, 1.0, -0.2, 128.0, 0.0)[c]:
+                assert g == out[c], (p, g, out[c])
+            continue
+        assert np.all(np.abs(g - want) <= FP32_GAUSS_TOL * scale), (op, p, g, want)
+
+
+def test_otsu_full_size(dev):
+    v = phantoms.porous_u16((1024, 1024, 1024), seed=0, device=dev)
+    print("full-size otsu u16", flush=True)
+    out, k = h.otsu(v)
+    torch.cuda.synchronize()
+    vnp = v.cpu().to(torch.int32).numpy()
+    assert k == oracle.otsu_threshold(vnp, 65536)
+    pts = sample_points(tuple(v.shape), 256, seed=5)
+    idx = torch.tensor(pts, device=dev)
+    vs = v.to(torch.int32)[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    os_ = out[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    np.testing.assert_array_equal(os_, (vs > k).astype(np.uint8))
+    assert int(out.sum(dtype=torch.int64)) == int(np.count_nonzero(vnp > k))
