@@ -132,7 +132,7 @@ struct StoreOut {
 // correlation, v[i + k] weighted by c_k); even taps otherwise.
 template <typename Tin, int R, int D, class Out, int PAR = 0>
 __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &taps, int zlen, int bx, int by,
-                                           int bz, Out &out)
+                                           int bz, int rot, Out &out)
 {
     constexpr int P = 2 * R + 1;
     constexpr int PW = kTX + 2 * R;  // patch columns
@@ -220,6 +220,11 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
     const int64_t gx_out = x0 + qcol;
     const int nvalid = (gy_out < yend) ? (int)min((int64_t)4, xend - gx_out) : 0;
     const int64_t col_off = (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
+    // y-pass items are dealt to the threads rotated by rot whole waves: NYI
+    // is rarely a multiple of the workgroup, and rotating which waves take
+    // the extra items between neighbouring workgroups spreads that work over
+    // the SIMDs of a CU instead of loading the same SIMD in every workgroup.
+    const int ytid = (tid + rot * 64) & (kNT - 1);
     const int64_t in_col_off = (gy_out - a.in_o[1]) * a.in_sy + (gx_out - a.in_o[2]);
 
     float acc[P][4];
@@ -287,7 +292,7 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
                 float *q = sQ + (i & 1) * QSZ;
 #pragma unroll
                 for (int itk = 0; itk < (NYI + kNT - 1) / kNT; ++itk) {
-                    const int it = tid + itk * kNT;
+                    const int it = ytid + itk * kNT;
                     if (itk == (NYI + kNT - 1) / kNT - 1 && it >= NYI) continue;
                     const int col = it % PW, rg = it / PW;
                     float v[kMY + 2 * R];
@@ -587,9 +592,10 @@ __global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps
                                                           int tiles_y)
 {
     int bx, by, bz;
-    tile_of_block(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, bx, by, bz);
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    tile_of_block(b, tiles_x, tiles_y, bx, by, bz);
     StoreOut<Tin, Tout, UNSHARP> out{static_cast<Tout *>(a.out), static_cast<const Tin *>(a.in), taps.amount};
-    gauss_tile<Tin, R, D, StoreOut<Tin, Tout, UNSHARP>, PAR>(a, taps, zlen, bx, by, bz, out);
+    gauss_tile<Tin, R, D, StoreOut<Tin, Tout, UNSHARP>, PAR>(a, taps, zlen, bx, by, bz, (int)(b & 3u), out);
 }
 
 // Persistent batched Gaussian: workgroup b takes work items
@@ -604,7 +610,7 @@ __global__ __launch_bounds__(kNT) void gauss_batched_kernel(BatchDesc d, GaussTa
         batch_item(d, w, c, bx, by, bz);
         const ChunkArgs a = crop_args(d.c[c]);
         StoreOut<Tin, Tout> out{static_cast<Tout *>(a.out), static_cast<const Tin *>(a.in), taps.amount};
-        gauss_tile<Tin, R, D>(a, taps, d.c[c].zlen, bx, by, bz, out);
+        gauss_tile<Tin, R, D>(a, taps, d.c[c].zlen, bx, by, bz, w & 3, out);
         lds_barrier();
     }
 }
