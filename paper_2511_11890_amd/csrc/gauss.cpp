@@ -5,9 +5,11 @@
 // with half-sample reflection R and normalised sampled taps (FP64 -> FP32).
 //
 // Fused kernel (equal radius r on all axes, 1 <= r <= kGaussFusedMaxR):
-//   one 256-thread workgroup owns a kTX x kTY tile of output columns and
-//   streams along z over a range of output slices.  Per input slice it
-//     1. stages the (kTX+2r) x (kTY+2r) patch in LDS (reflection applied on
+//   one workgroup owns a TX x 16 tile of output columns (TX = 128 with 512
+//   threads for r <= 6, TX = 64 with 256 threads above; one 4-column quad
+//   per thread) and streams along z over a range of output slices.  Per
+//   input slice it
+//     1. stages the (TX+2r) x (16+2r) patch in LDS (reflection applied on
 //        load, converted to f32) -- the global loads of the next slice are
 //        issued before the current slice is filtered, so HBM latency hides
 //        behind the LDS work;

@@ -12,6 +12,12 @@ namespace gauss_detail {
 constexpr int kTX = 64;  // tile columns (x)
 constexpr int kTY = 16;  // tile rows (y)
 
+// Tile width of the plain fused Gaussian: 128 columns (512 threads) for
+// radii up to 6, so a patch row spans fewer partial 128-byte lines per
+// output; 64 columns (256 threads) above, where the register ring and the
+// LDS patch grow with r.
+constexpr int fused_tx(int r) { return r <= 6 ? 128 : 64; }
+
 struct FusedGrid {
     int tiles_x, tiles_y, zlen;
     int64_t blocks;
@@ -22,10 +28,10 @@ struct FusedGrid {
 constexpr int64_t kMaxZRanges = 64;
 
 // ranges > 0: split z into that many ranges (the autotuner's choice).
-inline FusedGrid fused_grid(const ChunkArgs &a, int R, int64_t capacity, int ranges = 0)
+inline FusedGrid fused_grid(const ChunkArgs &a, int R, int64_t capacity, int ranges = 0, int tx = kTX)
 {
     FusedGrid g;
-    g.tiles_x = (int)((a.out_e[2] + kTX - 1) / kTX);
+    g.tiles_x = (int)((a.out_e[2] + tx - 1) / tx);
     g.tiles_y = (int)((a.out_e[1] + kTY - 1) / kTY);
     const int64_t tiles = (int64_t)g.tiles_x * g.tiles_y;
     int64_t nzc = z_ranges(a.out_e[0], tiles, capacity, R, kMaxZRanges);
@@ -33,13 +39,6 @@ inline FusedGrid fused_grid(const ChunkArgs &a, int R, int64_t capacity, int ran
     g.zlen = (int)((a.out_e[0] + nzc - 1) / nzc);
     g.blocks = tiles * ((a.out_e[0] + g.zlen - 1) / g.zlen);
     return g;
-}
-
-// Upper bound of fused_grid(...).blocks over every capacity.
-inline int64_t fused_blocks_bound(const ChunkArgs &a)
-{
-    const int64_t tiles = ((a.out_e[2] + kTX - 1) / kTX) * ((a.out_e[1] + kTY - 1) / kTY);
-    return tiles * (a.out_e[0] < kMaxZRanges ? a.out_e[0] : kMaxZRanges);
 }
 
 inline bool fused_ok(const GaussTaps &t, const ChunkArgs &a)

@@ -6,9 +6,11 @@
 // with half-sample reflection R and normalised sampled taps (FP64 -> FP32).
 //
 // Fused kernel (equal radius r on all axes, 1 <= r <= kGaussFusedMaxR):
-//   one 256-thread workgroup owns a kTX x kTY tile of output columns and
-//   streams along z over a range of output slices.  Per input slice it
-//     1. stages the (kTX+2r) x (kTY+2r) patch in LDS (reflection applied on
+//   one workgroup owns a TX x 16 tile of output columns (TX = 128 with 512
+//   threads for r <= 6, TX = 64 with 256 threads above; one 4-column quad
+//   per thread) and streams along z over a range of output slices.  Per
+//   input slice it
+//     1. stages the (TX+2r) x (16+2r) patch in LDS (reflection applied on
 //        load, converted to f32) -- the global loads of the next slice are
 //        issued before the current slice is filtered, so HBM latency hides
 //        behind the LDS work;
@@ -130,15 +132,16 @@ struct StoreOut {
 // PAR: bit a set (z = 1, y = 2, x = 4) when the taps of axis a are odd,
 // c_{-k} = -c_k and c_0 = 0, with w[k] = c_k for k >= 1 (a first-derivative
 // correlation, v[i + k] weighted by c_k); even taps otherwise.
-template <typename Tin, int R, int D, class Out, int PAR = 0>
+template <typename Tin, int R, int D, class Out, int PAR = 0, int TX = kTX>
 __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &taps, int zlen, int bx, int by,
                                            int bz, int rot, Out &out)
 {
+    constexpr int NT = TX / 4 * kTY;  // threads: one 4-column quad each
     constexpr int P = 2 * R + 1;
-    constexpr int PW = kTX + 2 * R;  // patch columns
+    constexpr int PW = TX + 2 * R;  // patch columns
     constexpr int PH = kTY + 2 * R;  // patch rows
     constexpr int PSZ = PW * PH;
-    constexpr int NLD = (PSZ + kNT - 1) / kNT;
+    constexpr int NLD = (PSZ + NT - 1) / NT;
     constexpr int QP = (PW + 3) & ~3;  // y-pass output pitch, 16-byte rows
     constexpr int NYI = PW * (kTY / kMY);
     constexpr int NH = 4 + 2 * R;  // x-pass inputs per quad
@@ -154,7 +157,7 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
     const int tid = threadIdx.x;
     const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
     const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1];
-    const int64_t x0 = xbeg + (int64_t)bx * kTX;
+    const int64_t x0 = xbeg + (int64_t)bx * TX;
     const int64_t y0 = ybeg + (int64_t)by * kTY;
     const int64_t zo0 = a.out_o[0] + (int64_t)bz * zlen;
     const int64_t zo1 = min(zo0 + (int64_t)zlen, a.out_o[0] + a.out_e[0]);
@@ -175,7 +178,7 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
     int32_t off[NLD];
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
-        const int e = tid + i * kNT;
+        const int e = tid + i * NT;
         off[i] = 0;
         if (e < PSZ) {
             const int row = e / PW, col = e - (e / PW) * PW;
@@ -205,17 +208,17 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
         const Tin *base = in + zl * a.in_sz;
 #pragma unroll
         for (int k = 0; k < NLD; ++k)
-            if (k < NLD - 1 || tid + k * kNT < PSZ) dst[k] = base[off[k]];
+            if (k < NLD - 1 || tid + k * NT < PSZ) dst[k] = base[off[k]];
     };
     auto stage = [&](int j, const Tin(&src)[NLD]) __attribute__((always_inline)) {
         float *dst = sP + (j & 1) * PSZ;
 #pragma unroll
         for (int k = 0; k < NLD; ++k)
-            if (k < NLD - 1 || tid + k * kNT < PSZ) dst[tid + k * kNT] = to_f32(src[k]);
+            if (k < NLD - 1 || tid + k * NT < PSZ) dst[tid + k * NT] = to_f32(src[k]);
     };
 
-    const int qrow = tid / (kTX / 4);
-    const int qcol = (tid % (kTX / 4)) * 4;
+    const int qrow = tid / (TX / 4);
+    const int qcol = (tid % (TX / 4)) * 4;
     const int64_t gy_out = y0 + qrow;
     const int64_t gx_out = x0 + qcol;
     const int nvalid = (gy_out < yend) ? (int)min((int64_t)4, xend - gx_out) : 0;
@@ -224,7 +227,7 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
     // is rarely a multiple of the workgroup, and rotating which waves take
     // the extra items between neighbouring workgroups spreads that work over
     // the SIMDs of a CU instead of loading the same SIMD in every workgroup.
-    const int ytid = (tid + rot * 64) & (kNT - 1);
+    const int ytid = (tid + rot * 64) & (NT - 1);
     const int64_t in_col_off = (gy_out - a.in_o[1]) * a.in_sy + (gx_out - a.in_o[2]);
 
     float acc[P][4];
@@ -291,9 +294,9 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &
                 const float *p = sP + (i & 1) * PSZ;
                 float *q = sQ + (i & 1) * QSZ;
 #pragma unroll
-                for (int itk = 0; itk < (NYI + kNT - 1) / kNT; ++itk) {
-                    const int it = ytid + itk * kNT;
-                    if (itk == (NYI + kNT - 1) / kNT - 1 && it >= NYI) continue;
+                for (int itk = 0; itk < (NYI + NT - 1) / NT; ++itk) {
+                    const int it = ytid + itk * NT;
+                    if (itk == (NYI + NT - 1) / NT - 1 && it >= NYI) continue;
                     const int col = it % PW, rg = it / PW;
                     float v[kMY + 2 * R];
 #pragma unroll
@@ -588,14 +591,15 @@ __device__ __forceinline__ void tile_of_block(uint32_t b, int tiles_x, int tiles
 }
 
 template <typename Tin, typename Tout, int R, bool UNSHARP = false, int PAR = 0, int D = gauss_prefetch_depth(R)>
-__global__ __launch_bounds__(kNT) void gauss_fused_kernel(ChunkArgs a, GaussTaps taps, int zlen, int tiles_x,
-                                                          int tiles_y)
+__global__ __launch_bounds__(fused_tx(R) / 4 * kTY) void gauss_fused_kernel(ChunkArgs a, GaussTaps taps, int zlen,
+                                                                          int tiles_x, int tiles_y)
 {
     int bx, by, bz;
     const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
     tile_of_block(b, tiles_x, tiles_y, bx, by, bz);
     StoreOut<Tin, Tout, UNSHARP> out{static_cast<Tout *>(a.out), static_cast<const Tin *>(a.in), taps.amount};
-    gauss_tile<Tin, R, D, StoreOut<Tin, Tout, UNSHARP>, PAR>(a, taps, zlen, bx, by, bz, (int)(b & 3u), out);
+    gauss_tile<Tin, R, D, StoreOut<Tin, Tout, UNSHARP>, PAR, fused_tx(R)>(a, taps, zlen, bx, by, bz, (int)(b & 3u),
+                                                                        out);
 }
 
 // Persistent batched Gaussian: workgroup b takes work items
@@ -648,12 +652,13 @@ __global__ __launch_bounds__(256) void gauss_pass_kernel(const Tin *src, int64_t
 template <typename Tin, typename Tout, int R, bool UNSHARP, int PAR = 0>
 void launch_fused_u(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
-    static const int64_t cap = resident_blocks(gauss_fused_kernel<Tin, Tout, R, UNSHARP, PAR>, kNT);
+    constexpr int NT = fused_tx(R) / 4 * kTY;
+    static const int64_t cap = resident_blocks(gauss_fused_kernel<Tin, Tout, R, UNSHARP, PAR>, NT);
     Tile t;
     const int code = tune_type_code<Tin>() * 8 + tune_type_code<Tout>() + (UNSHARP ? 64 : 0) + PAR * 128;
     const bool tuned = tune_lookup(TF_GAUSS, tune_key_volume(TF_GAUSS, R, code, a.out_e), t);
-    const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0);
-    hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R, UNSHARP, PAR>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s,
+    const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0, fused_tx(R));
+    hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R, UNSHARP, PAR>), dim3((uint32_t)g.blocks), dim3(NT), 0, s,
                        a, taps, g.zlen, g.tiles_x, g.tiles_y);
 }
 
