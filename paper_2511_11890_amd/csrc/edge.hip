@@ -4,8 +4,8 @@
 //         [1, 2, 1] Sobel, [1, 1, 1] Prewitt, along the two other axes),
 //   out = sqrt(G_z^2 + G_y^2 + G_x^2), reflect boundary.
 //
-// One z-streaming launch: a 256-thread workgroup owns a 64 x 16 tile of
-// output columns.  Per input slice it stages the 66 x 18 patch in LDS
+// One z-streaming launch: a 512-thread workgroup owns a 128 x 16 tile of
+// output columns.  Per input slice it stages the 130 x 18 patch in LDS
 // (double-buffered, reflection applied to the load addresses; the next
 // slice is loaded into registers while the current one is filtered), and
 // each thread forms, for its 4 columns, the three in-plane responses
@@ -20,8 +20,8 @@
 namespace harpia {
 namespace edge_detail {
 
-constexpr int kNT = 256;
-constexpr int kTX = 64, kTY = 16;
+constexpr int kNT = 512;
+constexpr int kTX = 128, kTY = 16;  // one 4-column quad per thread
 constexpr int PW = kTX + 2, PH = kTY + 2;
 constexpr int PWP = (PW + 3) & ~3;  // 16-byte rows
 constexpr int PSZ = PH * PWP;

@@ -18,8 +18,12 @@
 namespace harpia {
 namespace thresh_detail {
 
-constexpr int kNT = 256;
-constexpr int kTX = 64, kTY = 16, kMY = 4;
+constexpr int kTY = 16, kMY = 4;
+// Tile width: 128 columns (512 threads) while the register ring of 2r + 1
+// slices x NCH channels stays small, else 64 columns (256 threads); one
+// 4-column quad per thread.
+constexpr int thresh_tx(int r, int nch) { return (2 * r + 1) * nch <= 13 ? 128 : 64; }
+constexpr int thresh_nt(int r, int nch) { return thresh_tx(r, nch) / 4 * kTY; }
 constexpr int kMaxR1 = 12;  // one channel
 constexpr int kMaxR2 = 6;   // two channels (the ring doubles)
 
@@ -41,12 +45,13 @@ __device__ __forceinline__ uint8_t decide(const Params &p, float x, float m, flo
 }
 
 template <typename Tin, int R, int NCH>
-__global__ __launch_bounds__(kNT) void thresh_kernel(ChunkArgs a, GaussTaps taps, Params prm, int zlen, int tiles_x,
+__global__ __launch_bounds__(thresh_nt(R, NCH)) void thresh_kernel(ChunkArgs a, GaussTaps taps, Params prm, int zlen, int tiles_x,
                                                      int tiles_y)
 {
+    constexpr int TX = thresh_tx(R, NCH), NT = thresh_nt(R, NCH);
     constexpr int P = 2 * R + 1;
-    constexpr int PW = kTX + 2 * R, PH = kTY + 2 * R, PSZ = PW * PH;
-    constexpr int NLD = (PSZ + kNT - 1) / kNT;
+    constexpr int PW = TX + 2 * R, PH = kTY + 2 * R, PSZ = PW * PH;
+    constexpr int NLD = (PSZ + NT - 1) / NT;
     constexpr int QP = (PW + 3) & ~3;
     constexpr int NYI = PW * (kTY / kMY);
     constexpr int NH = 4 + 2 * R, NH4 = (NH + 3) / 4;
@@ -61,7 +66,7 @@ __global__ __launch_bounds__(kNT) void thresh_kernel(ChunkArgs a, GaussTaps taps
     const int tid = threadIdx.x;
     const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
     const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1];
-    const int64_t x0 = xbeg + (int64_t)bx * kTX, y0 = ybeg + (int64_t)by * kTY;
+    const int64_t x0 = xbeg + (int64_t)bx * TX, y0 = ybeg + (int64_t)by * kTY;
     const int64_t zo0 = a.out_o[0] + (int64_t)bz * zlen;
     const int64_t zo1 = min(zo0 + (int64_t)zlen, a.out_o[0] + a.out_e[0]);
     if (zo0 >= zo1) return;
@@ -77,7 +82,7 @@ __global__ __launch_bounds__(kNT) void thresh_kernel(ChunkArgs a, GaussTaps taps
     int32_t off[NLD];
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
-        const int e = tid + i * kNT;
+        const int e = tid + i * NT;
         off[i] = 0;
         if (e < PSZ) {
             const int row = e / PW, col = e - row * PW;
@@ -98,16 +103,16 @@ __global__ __launch_bounds__(kNT) void thresh_kernel(ChunkArgs a, GaussTaps taps
         const Tin *base = in + (reflect_index(s0 + j, a.n[0]) - a.in_o[0]) * a.in_sz;
 #pragma unroll
         for (int k = 0; k < NLD; ++k)
-            if (k < NLD - 1 || tid + k * kNT < PSZ) pf[k] = base[off[k]];
+            if (k < NLD - 1 || tid + k * NT < PSZ) pf[k] = base[off[k]];
     };
     auto stage = [&](int j) __attribute__((always_inline)) {
         float *dst = sP + (j & 1) * PSZ;
 #pragma unroll
         for (int k = 0; k < NLD; ++k)
-            if (k < NLD - 1 || tid + k * kNT < PSZ) dst[tid + k * kNT] = to_f32(pf[k]);
+            if (k < NLD - 1 || tid + k * NT < PSZ) dst[tid + k * NT] = to_f32(pf[k]);
     };
 
-    const int qrow = tid / (kTX / 4), qcol = (tid % (kTX / 4)) * 4;
+    const int qrow = tid / (TX / 4), qcol = (tid % (TX / 4)) * 4;
     const int64_t gy_out = y0 + qrow, gx_out = x0 + qcol;
     const int nvalid = (gy_out < yend) ? (int)min((int64_t)4, xend - gx_out) : 0;
     uint8_t *outp = static_cast<uint8_t *>(a.out) + (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
@@ -165,9 +170,9 @@ __global__ __launch_bounds__(kNT) void thresh_kernel(ChunkArgs a, GaussTaps taps
                 // y pass of slice i: channel 0 weights v, channel 1 v^2
                 const float *p = sP + (i & 1) * PSZ;
 #pragma unroll
-                for (int itk = 0; itk < (NYI + kNT - 1) / kNT; ++itk) {
-                    const int it = tid + itk * kNT;
-                    if (itk == (NYI + kNT - 1) / kNT - 1 && it >= NYI) continue;
+                for (int itk = 0; itk < (NYI + NT - 1) / NT; ++itk) {
+                    const int it = tid + itk * NT;
+                    if (itk == (NYI + NT - 1) / NT - 1 && it >= NYI) continue;
                     const int col = it % PW, rg = it / PW;
                     float v[kMY + 2 * R];
 #pragma unroll
@@ -223,13 +228,14 @@ __global__ __launch_bounds__(kNT) void thresh_kernel(ChunkArgs a, GaussTaps taps
 template <typename Tin, int R, int NCH>
 void launch(const ChunkArgs &a, const GaussTaps &taps, const Params &prm, hipStream_t s)
 {
-    static const int64_t cap = resident_blocks(thresh_kernel<Tin, R, NCH>, kNT);
-    const int tiles_x = (int)((a.out_e[2] + kTX - 1) / kTX), tiles_y = (int)((a.out_e[1] + kTY - 1) / kTY);
+    constexpr int TX = thresh_tx(R, NCH), NT = thresh_nt(R, NCH);
+    static const int64_t cap = resident_blocks(thresh_kernel<Tin, R, NCH>, NT);
+    const int tiles_x = (int)((a.out_e[2] + TX - 1) / TX), tiles_y = (int)((a.out_e[1] + kTY - 1) / kTY);
     const int64_t tiles = (int64_t)tiles_x * tiles_y;
     const int64_t nzc = z_ranges(a.out_e[0], tiles, cap, R, 64);
     const int zlen = (int)((a.out_e[0] + nzc - 1) / nzc);
     const int64_t blocks = tiles * ((a.out_e[0] + zlen - 1) / zlen);
-    hipLaunchKernelGGL((thresh_kernel<Tin, R, NCH>), dim3((uint32_t)blocks), dim3(kNT), 0, s, a, taps, prm, zlen,
+    hipLaunchKernelGGL((thresh_kernel<Tin, R, NCH>), dim3((uint32_t)blocks), dim3(NT), 0, s, a, taps, prm, zlen,
                        tiles_x, tiles_y);
 }
 
