@@ -5,7 +5,8 @@
 //   niblack:  T = m + k s,                   s = sqrt(mean(v^2) - m^2),
 //   sauvola:  T = m (1 + k (s / R - 1)).
 // One z-streaming launch per chunk on the skeleton of the fused Gaussian:
-// a 64 x 16 tile of output columns, the (64+2r) x (16+2r) patch staged in
+// a TX x 16 tile of output columns (TX = 128 or 64, see thresh_tx), the
+// (TX+2r) x (16+2r) patch staged in
 // LDS per slice (the next slice loaded into registers meanwhile), y and x
 // passes from LDS and a z ring of 2r+1 partial sums per column in
 // registers -- one channel (the weighted mean), or two (v and v^2) for the
