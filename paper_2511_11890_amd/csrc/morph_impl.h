@@ -111,17 +111,18 @@ struct Out2 {
     int64_t sy, sz;
 };
 
-template <typename T, int SE, int R, bool BOTH>
+template <typename T, int SE, int R, bool BOTH, int TX = kGTX>
 __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, float sign, int zlen, int bx, int by,
                                           int bz)
 {
     using S = Shape<SE, R>;
+    constexpr int NT = TX / kGC * kGTY;  // threads: kGC columns each
     constexpr int P = 2 * R + 1;
-    constexpr int PW = kGTX + 2 * R;
+    constexpr int PW = TX + 2 * R;
     constexpr int PWP = (PW + 3) & ~3;
     constexpr int PH = kGTY + 2 * R;
     constexpr int PSZ = PW * PH;
-    constexpr int NLD = (PSZ + kGNT - 1) / kGNT;
+    constexpr int NLD = (PSZ + NT - 1) / NT;
     constexpr int NV = kGC + 2 * R;               // patch columns one thread reads per row
     constexpr int NV4 = (NV + 3) / 4;
     constexpr int NM = BOTH ? 2 : 1;      // 0: max (dilation), 1: min
@@ -136,7 +137,7 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
     const int tid = threadIdx.x;
     const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
     const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1];
-    const int64_t x0 = xbeg + (int64_t)bx * kGTX;
+    const int64_t x0 = xbeg + (int64_t)bx * TX;
     const int64_t y0 = ybeg + (int64_t)by * kGTY;
     const int64_t zo0 = a.out_o[0] + (int64_t)bz * zlen;
     const int64_t zo1 = min(zo0 + (int64_t)zlen, a.out_o[0] + a.out_e[0]);
@@ -146,7 +147,7 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
     int32_t lds[NLD];
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
-        const int e = tid + i * kGNT;
+        const int e = tid + i * NT;
         off[i] = 0;
         lds[i] = 0;
         if (e < PSZ) {
@@ -173,11 +174,11 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
         const T *base = in + (reflect_index(s0 + j, a.n[0]) - a.in_o[0]) * a.in_sz;
 #pragma unroll
         for (int i = 0; i < NLD; ++i)
-            if (i < NLD - 1 || tid + i * kGNT < PSZ) pf[i] = base[off[i]];
+            if (i < NLD - 1 || tid + i * NT < PSZ) pf[i] = base[off[i]];
     };
 
-    const int qrow = tid / (kGTX / kGC);
-    const int qcol = (tid % (kGTX / kGC)) * kGC;
+    const int qrow = tid / (TX / kGC);
+    const int qcol = (tid % (TX / kGC)) * kGC;
     const int64_t gy_out = y0 + qrow;
     const int64_t gx_out = x0 + qcol;
     const int nvalid = (gy_out < yend) ? (int)min((int64_t)kGC, xend - gx_out) : 0;
@@ -206,7 +207,7 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
             if (i < nsteps) {
 #pragma unroll
                 for (int k = 0; k < NLD; ++k)
-                    if (k < NLD - 1 || tid + k * kGNT < PSZ)
+                    if (k < NLD - 1 || tid + k * NT < PSZ)
                         buf[lds[k]] = BOTH ? to_f32(pf[k]) : sign * to_f32(pf[k]);
                 fetch(i + 1);
             }
@@ -305,15 +306,22 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
     }
 }
 
+// Tile width of the single-volume kernel: 128 columns (1024 threads) up to
+// radius 3, so a patch row spans fewer partial 128-byte lines per output;
+// 64 columns (512 threads) at radius 4, whose registers would not fit the
+// wider workgroup.
+constexpr int gray_tx(int r) { return r <= 3 ? 128 : kGTX; }
+constexpr int gray_nt(int r) { return gray_tx(r) / kGC * kGTY; }
+
 template <typename T, int SE, int R, bool BOTH>
-__global__ __launch_bounds__(kGNT) void gray_kernel(ChunkArgs a, Out2 o2, float sign, int tiles_x, int tiles_y,
+__global__ __launch_bounds__(gray_nt(R)) void gray_kernel(ChunkArgs a, Out2 o2, float sign, int tiles_x, int tiles_y,
                                                    int zlen)
 {
     const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = (int)(b % (uint32_t)tiles_x);
     const int by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
     const int bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
-    gray_tile<T, SE, R, BOTH>(a, o2, sign, zlen, bx, by, bz);
+    gray_tile<T, SE, R, BOTH, gray_tx(R)>(a, o2, sign, zlen, bx, by, bz);
 }
 
 // Persistent batched grayscale morphology (in -> out, aux -> second output
@@ -624,12 +632,12 @@ void launch_fast(const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float t
                            (uint32_t)(m.op == 0 ? 1u : 0u), thr_f, (int)m.has_threshold, g.tiles_x, g.tiles_y,
                            g.zlen);
     } else {
-        static const int64_t cap = resident_blocks(gray_kernel<T, SE, R, BOTH>, kGNT);
+        static const int64_t cap = resident_blocks(gray_kernel<T, SE, R, BOTH>, gray_nt(R));
         Tile t;
         const bool tuned = tune_lookup(
             TF_GRAY, tune_key_volume(TF_GRAY, R * 4 + SE * 2 + (BOTH ? 1 : 0), tune_type_code<T>(), a.out_e), t);
-        const Grid g = make_grid(a, kGTX, kGTY, R, cap, tuned ? t.tz : 0);
-        hipLaunchKernelGGL((gray_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kGNT), 0, s, a, o2,
+        const Grid g = make_grid(a, gray_tx(R), kGTY, R, cap, tuned ? t.tz : 0);
+        hipLaunchKernelGGL((gray_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(gray_nt(R)), 0, s, a, o2,
                            m.op == 0 ? -1.f : 1.f, g.tiles_x, g.tiles_y, g.zlen);
     }
 }
