@@ -85,6 +85,10 @@ typedef enum harpia_morph_op { HARPIA_ERODE = 0, HARPIA_DILATE = 1 } harpia_morp
                                        is uint8 {0, 1} */
 #define HARPIA_F_FORCE_CHUNKED 0x2u /* device path: use the chunk engine even
                                        when the whole volume fits the budget */
+#define HARPIA_F_SIGMA_SUM 0x4u     /* Gaussian backward: grad_sigma receives
+                                       one double, the sum of the three axis
+                                       terms (the gradient of an isotropic
+                                       sigma), reduced on the device in FP64 */
 
 /* Optional per-call statistics (filled when harpia_exec.stats != NULL). */
 typedef struct harpia_stats {
@@ -94,15 +98,24 @@ typedef struct harpia_stats {
     int64_t peak_device_bytes; /* library-owned device bytes at peak */
     int64_t budget_bytes;      /* budget the call ran under */
     double wall_ms;            /* host wall time of the call */
+    double kernel_ms;          /* host volumes: sum over chunks of the time
+                                  the filter kernels took (HIP events on the
+                                  compute stream around each chunk); 0 on
+                                  the device path */
 } harpia_stats;
 
 /* Execution options; a NULL harpia_exec* means all defaults. */
 typedef struct harpia_exec {
-    size_t device_budget_bytes; /* cap on library device memory; 0 => use
-                                   budget_fraction x free device memory */
+    size_t device_budget_bytes; /* cap on library device memory; the
+                                   budget is min(cap, budget_fraction x free
+                                   device memory); 0 => no cap (the
+                                   HARPIA_DEVICE_BUDGET environment variable,
+                                   in bytes, is the default cap) */
     double budget_fraction;     /* fraction of free device memory reserved
                                    for chunks (Section III-D, step 1);
-                                   0 => HARPIA_DEFAULT_BUDGET_FRACTION */
+                                   0 => HARPIA_BUDGET_FRACTION from the
+                                   environment, else
+                                   HARPIA_DEFAULT_BUDGET_FRACTION */
     int64_t chunk[3];           /* core chunk extent {z, y, x}; {0, 0, 0} =>
                                    the planner picks the deepest z-slab that
                                    fits (Section III-D, step 2) */
@@ -142,8 +155,9 @@ int32_t harpia_gauss_radius(double sigma, double truncate);
  * per side (Section III-D: query free memory, reserve a fixed fraction,
  * compute the largest chunk that fits with its padding).  in_t / out_t give
  * the bytes per voxel of the staged input and output chunks.  ex may be
- * NULL.  With ex->device_budget_bytes != 0 no device is queried, so this
- * call works without a GPU.
+ * NULL.  The budget is min(cap, fraction x free device memory); on a host
+ * without a GPU an explicit cap (ex->device_budget_bytes) is used as is, so
+ * plans can be made there.
  * Errors: HARPIA_ERR_ARG (shape <= 0, halo < 0, out == NULL),
  *         HARPIA_ERR_DTYPE, HARPIA_ERR_BUDGET (a 1-slice chunk with its halo
  *         does not fit), HARPIA_ERR_HIP (free-memory query failed). */
@@ -315,10 +329,12 @@ harpia_status harpia_morph3d(const void *in, void *out, harpia_dtype t,
  *     to grad_out.  May be NULL.  float32.
  *   grad_sigma[a] = sum_p grad_out[p] * (d/d sigma_a (G x))[p] with the
  *     radii held fixed (d w_k / d sigma = w_k (k^2 - sum_j w_j j^2) / sigma^3),
- *     a = z, y, x; an isotropic sigma's gradient is the sum of the three.
- *     FP32 products summed per workgroup, workgroup partials summed in FP64
- *     in a fixed order (deterministic).  May be NULL, a host pointer (filled
- *     before return) or a device pointer (written on ex->stream).
+ *     a = z, y, x: three doubles.  With HARPIA_F_SIGMA_SUM in ex->flags it
+ *     is one double, the sum of the three (the gradient of an isotropic
+ *     sigma, used for all three axes).  FP32 products summed per workgroup,
+ *     workgroup partials summed in FP64 in a fixed order (deterministic).
+ *     May be NULL, a host pointer (filled before return) or a device pointer
+ *     (written on ex->stream).
  * x (dtype x_t, as for harpia_gaussian3d) is needed only for grad_sigma.
  * radius[3]: the radii the forward used (resolve them once with
  * harpia_gauss_radius and keep them; they are not recomputed from sigma). */
@@ -347,9 +363,9 @@ harpia_status harpia_morph3d_backward(const void *in, harpia_dtype t,
 /* ------------------------------------------------------------------
  * Batched crops (an extension beyond the paper: many uneven volumes, e.g.
  * training crops or the edge chunks of a volume, in one persistent launch).
- * Each launch takes up to 32 crops whose (crop, tile) work items are strided
+ * Each launch takes up to 64 crops whose (crop, tile) work items are strided
  * over the resident workgroups; larger batches are split into launches of
- * 32.  The crop table is passed by value in the kernel arguments, so these
+ * 64.  The crop table is passed by value in the kernel arguments, so these
  * calls allocate nothing and may be captured in a HIP graph.  All volumes
  * are dense float32 [nz][ny][nx] in device memory; calls are asynchronous on
  * ex->stream.
@@ -383,7 +399,8 @@ harpia_status harpia_morph3d_batched(const harpia_crop *crops, int32_t n_crops,
 /* Gaussian gradients over a batch, radii held fixed (equal, 1..12):
  * per crop in = x, aux = grad_out, out = grad_in (NULL on every crop to
  * skip).  grad_sigma (device pointer, 3 doubles, or NULL) receives
- * d/d sigma_{z,y,x} summed over all crops (one sigma shared by the batch):
+ * d/d sigma_{z,y,x} summed over all crops (one sigma shared by the batch);
+ * with HARPIA_F_SIGMA_SUM in ex->flags, one double: the sum of the three.
  * FP32 workgroup partials in `workspace`, reduced in FP64 in fixed order. */
 harpia_status harpia_gaussian3d_backward_batched(const harpia_crop *crops,
                                                  int32_t n_crops,

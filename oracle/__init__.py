@@ -141,6 +141,14 @@ def num_threads() -> int:
     return int(_load().oracle_num_threads())
 
 
+def set_threads(n: int) -> None:
+    """Worker threads of later oracle calls from this thread (OpenMP's
+    omp_set_num_threads of the runtime the oracle is linked against); used
+    to time the oracle on one core and on all cores."""
+    _load()
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
 # ---------------------------------------------------------------- Gaussian
 
 def _radii(sigma, truncate, radius):

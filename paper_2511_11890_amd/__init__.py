@@ -358,18 +358,21 @@ def plan(shape, in_dtype="f32", out_dtype="f32", halo=(0, 0, 0), budget: int = 0
     return p
 
 
-def gaussian_backward(x, grad_out, sigma, radius, grad_in=True, grad_sigma=True, ex: Exec | None = None):
+def gaussian_backward(x, grad_out, sigma, radius, grad_in=True, grad_sigma=True, ex: Exec | None = None,
+                      sigma_sum: bool = False):
     """Gradients of y = gaussian(x, sigma) with the radii held fixed:
     (G^T grad_out or None, float64 tensor [3] of dL/d sigma_{z,y,x} or None).
+    With sigma_sum the second is a float64 tensor [1]: the gradient of an
+    isotropic sigma (the library sums the three axis terms on the device).
     Device tensors only; grad_out float32."""
     torch = _torch()
     _check_volume(grad_out)
     if grad_out.dtype != torch.float32:
         raise HarpiaError(_lib.HARPIA_ERR_DTYPE, "grad_out must be float32")
     gi = torch.empty_like(grad_out) if grad_in else None
-    gs = torch.zeros(3, dtype=torch.float64, device=grad_out.device) if grad_sigma else None
+    gs = torch.zeros(1 if sigma_sum else 3, dtype=torch.float64, device=grad_out.device) if grad_sigma else None
     xc = _dtype_code(x) if x is not None else _lib.HARPIA_F32
-    e = _exec(grad_out, ex)
+    e = _exec(grad_out, ex, _lib.HARPIA_F_SIGMA_SUM if sigma_sum else 0)
     with _device_guard(grad_out):
         _lib.check(_lib.load().harpia_gaussian3d_backward(
             _ptr(x) if x is not None else None, xc, _ptr(grad_out), _ptr(gi) if gi is not None else None,
@@ -404,12 +407,10 @@ def _sigma_values(sigma):
 
 
 def _sigma_grad(sigma, gs):
-    """dL/d sigma in the shape of `sigma`: an isotropic sigma gets the sum of
-    the three per-axis derivatives (chain rule)."""
+    """dL/d sigma in the shape of `sigma` (gs from gaussian_backward, with
+    sigma_sum for a one-element sigma)."""
     if gs is None:
         return None
-    if sigma.numel() == 1:
-        gs = gs.sum()
     return gs.to(device=sigma.device, dtype=sigma.dtype).reshape(sigma.shape)
 
 
@@ -451,7 +452,8 @@ class GaussianFn(metaclass=_LazyFunction):
                     x, sig = ctx.saved_tensors
                     need_s = sig is not None and ctx.needs_input_grad[1]
                     gx, gs = gaussian_backward(x.contiguous(), gy.contiguous().float(), ctx.s, ctx.r,
-                                               grad_in=ctx.needs_input_grad[0], grad_sigma=need_s)
+                                               grad_in=ctx.needs_input_grad[0], grad_sigma=need_s,
+                                               sigma_sum=need_s and sig.numel() == 1)
                     return (gx.to(x.dtype) if gx is not None else None,
                             _sigma_grad(sig, gs) if need_s else None, None)
 
@@ -519,7 +521,8 @@ class GaussDilateFn(metaclass=_LazyFunction):
                     del y
                     need_s = sig is not None and ctx.needs_input_grad[1]
                     gx, gs = gaussian_backward(x.contiguous(), gy, ctx.s, ctx.r,
-                                               grad_in=ctx.needs_input_grad[0], grad_sigma=need_s)
+                                               grad_in=ctx.needs_input_grad[0], grad_sigma=need_s,
+                                               sigma_sum=need_s and sig.numel() == 1)
                     return (gx.to(x.dtype) if gx is not None else None,
                             _sigma_grad(sig, gs) if need_s else None, None, None, None)
 
@@ -532,7 +535,7 @@ def _stream():
 
 
 def gaussian_batched(xs, sigma, truncate: float = 3.0, outs=None):
-    """Gaussian of every crop in one persistent launch per 32 crops (float32
+    """Gaussian of every crop in one persistent launch per 64 crops (float32
     device tensors of any shapes; equal radii 1..12)."""
     torch = _torch()
     outs = [torch.empty_like(x) for x in xs] if outs is None else outs
@@ -566,7 +569,8 @@ class GaussDilateBatch:
         fwd:  y = G x (batched), d = dilate(y) (batched)
         bwd:  y = G x recomputed, g_y = routed g_d (argext + gather, batched),
               g_x = G g_y (batched), d L / d sigma = sum_a <g_y, G'_a x>
-              (batched dot, FP64 reduction) -- kept on the device.
+              (batched dot, FP64 reduction, the three axis terms summed
+              on the device) -- kept on the device.
     sigma is a Python float (isotropic); its radius is resolved once."""
 
     def __init__(self, xs, sigma: float, se: str = "box", radius=2, truncate: float = 3.0):
@@ -580,7 +584,7 @@ class GaussDilateBatch:
         self.ds = [torch.empty_like(x) for x in xs]
         self.gys = [torch.empty_like(x) for x in xs]
         self.gxs = [torch.empty_like(x) for x in xs]
-        self.gsigma = torch.zeros(3, dtype=torch.float64, device=xs[0].device)
+        self.gsigma = torch.zeros(1, dtype=torch.float64, device=xs[0].device)
         self._c_fwd_g = _lib.crops([(x, y, None) for x, y in zip(xs, self.ys)])
         self._c_fwd_d = _lib.crops([(y, d, None) for y, d in zip(self.ys, self.ds)])
         nbytes = _lib.load().harpia_batch_workspace_bytes(self._c_fwd_g, len(xs))
@@ -599,8 +603,10 @@ class GaussDilateBatch:
 
     def backward(self, gds):
         """gds: upstream gradients (float32 tensors like the crops).  Returns
-        (grad_x list, dL/dsigma_{z,y,x} as a float64 device tensor)."""
+        (grad_x list, dL/dsigma of the isotropic sigma as a float64 device
+        tensor [1])."""
         lib, n, st = _lib.load(), len(self.xs), _lib.make_exec(stream=_stream())
+        st_sum = _lib.make_exec(stream=_stream(), flags=_lib.HARPIA_F_SIGMA_SUM)
         if self.gds is not gds:
             self.gds = gds
             self._c_bwd_m = _lib.crops([(y, gy, g) for y, gy, g in zip(self.ys, self.gys, gds)])
@@ -615,7 +621,7 @@ class GaussDilateBatch:
                                                        {"box": 0, "ball": 1}[self.se],
                                                        _lib.i32_3(_triple(self.mr, int)), ws, wsb, st))
         _lib.check(lib.harpia_gaussian3d_backward_batched(self._c_bwd_g, n, s3, r3, self.gsigma.data_ptr(), ws,
-                                                          wsb, st))
+                                                          wsb, st_sum))
         return self.gxs, self.gsigma
 
     def autotune(self, reps: int = 3):
@@ -646,16 +652,20 @@ def autotune_gaussian(x, sigma, out=None, truncate: float = 3.0, reps: int = 3):
     return rep.entries()
 
 
-def autotune_erode_dilate(x, se: str = "ball", radius=1, ero=None, dil=None, reps: int = 3):
-    """Autotune the grayscale erosion+dilation kernel on this volume."""
+def autotune_erode_dilate(x, se: str = "ball", radius=1, ero=None, dil=None, reps: int = 3,
+                          threshold=None, binary: bool = False):
+    """Autotune the erosion+dilation kernel on this volume (grayscale, or
+    binary with a threshold or binary=True; outputs then uint8)."""
     torch = _torch()
-    ero = torch.empty_like(x) if ero is None else ero
-    dil = torch.empty_like(x) if dil is None else dil
+    bin_out = binary or threshold is not None
+    ero = (torch.empty_like(x, dtype=torch.uint8) if bin_out else torch.empty_like(x)) if ero is None else ero
+    dil = (torch.empty_like(x, dtype=torch.uint8) if bin_out else torch.empty_like(x)) if dil is None else dil
     rep = _lib.harpia_tune_report()
     _lib.check(_lib.load().harpia_autotune_erode_dilate3d(
         x.data_ptr(), ero.data_ptr(), dil.data_ptr(), _dtype_code(x), _lib.i64_3(x.shape),
-        {"box": 0, "ball": 1}[se], _lib.i32_3(_triple(radius, int)), float("nan"), int(reps),
-        _lib.make_exec(stream=_stream()), _ctypes.byref(rep)))
+        {"box": 0, "ball": 1}[se], _lib.i32_3(_triple(radius, int)),
+        float("nan") if threshold is None else float(threshold), int(reps),
+        _lib.make_exec(stream=_stream(), flags=_lib.HARPIA_F_BINARY if binary else 0), _ctypes.byref(rep)))
     return rep.entries()
 
 

@@ -35,12 +35,14 @@ HARPIA_ERODE, HARPIA_DILATE = 0, 1
 # flags
 HARPIA_F_BINARY = 0x1
 HARPIA_F_FORCE_CHUNKED = 0x2
+HARPIA_F_SIGMA_SUM = 0x4
 
 
 class harpia_stats(ctypes.Structure):
     _fields_ = [("n_chunks", ctypes.c_int64), ("bytes_h2d", ctypes.c_int64),
                 ("bytes_d2h", ctypes.c_int64), ("peak_device_bytes", ctypes.c_int64),
-                ("budget_bytes", ctypes.c_int64), ("wall_ms", ctypes.c_double)]
+                ("budget_bytes", ctypes.c_int64), ("wall_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double)]
 
 
 class harpia_exec(ctypes.Structure):

@@ -213,7 +213,7 @@ harpia_status harpia_chunk_plan(const int64_t shape[3], harpia_dtype in_t, harpi
         for (int a = 0; a < 3; ++a) st.r[a] = halo[a];
         std::vector<Stage> stages{st};
         ChunkCost cost{true, dtype_size(in_t), dtype_size(out_t), 1, &stages};
-        const size_t budget = resolve_budget(ex, true);
+        const size_t budget = resolve_budget(ex);
         const int64_t zero[3] = {0, 0, 0};
         plan_chunks(shape, halo, ex ? ex->chunk : zero, cost, budget, 3, *out);
     });
@@ -558,6 +558,9 @@ harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t, const 
             check_hip(hipGetLastError(), "kernel launch");
         }
         if (grad_sigma) {
+            // HARPIA_F_SIGMA_SUM: one value, the sum of the three axis terms
+            const bool sum = ex && (ex->flags & HARPIA_F_SIGMA_SUM);
+            const int n_sig = sum ? 1 : 3;
             const bool dev_out = is_device_pointer(grad_sigma);
             double *dst = grad_sigma;
             if (!dev_out) {
@@ -578,8 +581,10 @@ harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t, const 
                                                        s, part);
                 if (nb < 0) fail(HARPIA_ERR_UNSUPPORTED, "no fused sigma-gradient kernel for these radii");
                 check_hip(hipGetLastError(), "kernel launch");
-                for (int axis = 0; axis < 3; ++axis) {
-                    launch_reduce_f64(part + axis * nb, nb, dst + axis, false, s);
+                // the three terms' partials are contiguous: their sum is one
+                // reduction over all of them
+                for (int axis = 0; axis < n_sig; ++axis) {
+                    launch_reduce_f64(part + axis * nb, sum ? 3 * nb : nb, dst + axis, false, s);
                     check_hip(hipGetLastError(), "kernel launch");
                 }
             }
@@ -600,11 +605,12 @@ harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t, const 
                 if (!partials.p) partials.alloc((size_t)max_blocks * sizeof(float));
                 const int64_t nb = launch_dot_partials(d_reg, g_reg, static_cast<float *>(partials.p), max_blocks, s);
                 check_hip(hipGetLastError(), "kernel launch");
-                launch_reduce_f64(static_cast<const float *>(partials.p), nb, dst + axis, false, s);
+                launch_reduce_f64(static_cast<const float *>(partials.p), nb, dst + (sum ? 0 : axis), sum && axis > 0,
+                                  s);
                 check_hip(hipGetLastError(), "kernel launch");
             }
             if (!dev_out)
-                check_hip(hipMemcpyAsync(grad_sigma, dst, 3 * sizeof(double), hipMemcpyDeviceToHost, s),
+                check_hip(hipMemcpyAsync(grad_sigma, dst, n_sig * sizeof(double), hipMemcpyDeviceToHost, s),
                           "hipMemcpyAsync");
             allocated = true;
         }
@@ -780,7 +786,7 @@ harpia_status harpia_gaussian3d_backward_batched(const harpia_crop *crops, int32
             const size_t need = (size_t)(3 * launches * gauss_batched_max_partials()) * sizeof(float);
             if (!workspace || workspace_bytes < need) fail(HARPIA_ERR_ARG, "workspace too small");
             if (!is_device_pointer(workspace)) fail(HARPIA_ERR_ARG, "workspace must be device memory");
-            // all three terms in one pass per launch of up to 32 crops; each
+            // all three terms in one pass per launch of up to 64 crops; each
             // launch's partials are reduced into grad_sigma in launch order
             GaussTaps wt3, dt3;
             make_gauss_taps_r(sigma, r, wt3);
@@ -792,7 +798,11 @@ harpia_status harpia_gaussian3d_backward_batched(const harpia_crop *crops, int32
                 const int64_t grid = launch_gauss_sigma3_batched(make_desc(crops, f, cnt, 2), wt3, dt3, s, pl);
                 if (grid < 0) fail(HARPIA_ERR_UNSUPPORTED, "no batched sigma-gradient kernel");
                 check_hip(hipGetLastError(), "kernel launch");
-                for (int axis = 0; axis < 3; ++axis) {
+                if (ex && (ex->flags & HARPIA_F_SIGMA_SUM)) {
+                    launch_reduce_f64(pl, 3 * grid, grad_sigma, l > 0, s);
+                    check_hip(hipGetLastError(), "kernel launch");
+                }
+                for (int axis = 0; axis < 3 && !(ex && (ex->flags & HARPIA_F_SIGMA_SUM)); ++axis) {
                     launch_reduce_f64(pl + axis * grid, grid, grad_sigma + axis, l > 0, s);
                     check_hip(hipGetLastError(), "kernel launch");
                 }

@@ -9,7 +9,7 @@
 
 namespace harpia {
 
-constexpr int kMaxBatch = 32;  // crops per launch; larger batches are split
+constexpr int kMaxBatch = 64;  // crops per launch; larger batches are split
 
 struct BatchCrop {
     const void *in;   // volume read
@@ -24,6 +24,12 @@ struct BatchDesc {
     int32_t prefix[kMaxBatch + 1];  // work items before crop c
     BatchCrop c[kMaxBatch];
 };
+
+// The largest batched kernel argument list (the sigma-gradient: descriptor,
+// two tap sets, partials pointer and stride) fits the 4 KiB kernel-argument
+// space.
+static_assert(sizeof(BatchDesc) + 2 * sizeof(FusedTaps) + 2 * sizeof(int64_t) <= 4096,
+              "batch descriptor too large for the kernel arguments");
 
 // Whole-volume chunk arguments of a crop (dense, origin 0).
 __host__ __device__ inline ChunkArgs crop_args(const BatchCrop &c)

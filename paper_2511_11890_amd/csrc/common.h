@@ -223,6 +223,23 @@ struct GaussTaps {
                                               // c_0 = 0, w[k] = c_k for k >= 1
 };
 
+// The taps a fused z-streaming kernel takes as a kernel argument (radii up
+// to kGaussFusedMaxR): 160 bytes instead of GaussTaps' 804, so that a
+// 64-crop batch descriptor plus two tap sets fit the 4 KiB argument space.
+struct FusedTaps {
+    float w[3][kGaussFusedMaxR + 1];  // half taps w[a][|k|], FP32
+    float amount;                     // unsharp mask amount
+};
+
+inline FusedTaps fused_taps(const GaussTaps &t)
+{
+    FusedTaps f;
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k <= kGaussFusedMaxR; ++k) f.w[a][k] = t.w[a][k];
+    f.amount = t.amount;
+    return f;
+}
+
 // Fills taps in FP64 and rounds them to FP32 (host).
 void make_gauss_taps(const double sigma[3], double truncate, GaussTaps &t);
 void make_gauss_taps_r(const double sigma[3], const int radius[3], GaussTaps &t);

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <thread>
 
@@ -102,7 +103,10 @@ struct StreamH {
 
 struct EventH {
     hipEvent_t e = nullptr;
-    EventH() { check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate"); }
+    explicit EventH(bool timing = false)
+    {
+        check_hip(hipEventCreateWithFlags(&e, timing ? hipEventDefault : hipEventDisableTiming), "hipEventCreate");
+    }
     EventH(const EventH &) = delete;
     EventH &operator=(const EventH &) = delete;
     ~EventH()
@@ -376,7 +380,7 @@ void run_device(const Job &job, harpia_stats *stats)
         return;
     }
 
-    const size_t budget = resolve_budget(ex, true);
+    const size_t budget = resolve_budget(ex);
     harpia_plan p;
     ChunkCost cost{false, in_es, out_es, job.out2 ? 2 : 1, &job.stages};
     int32_t halo[3] = {total_halo(job.stages, 0), total_halo(job.stages, 1), total_halo(job.stages, 2)};
@@ -438,7 +442,7 @@ void run_host(const Job &job, Mem min, Mem mout, harpia_stats *stats)
     const Stage &last = job.stages.back();
     const size_t in_es = dtype_size(first.in_t), out_es = dtype_size(last.out_t);
     const int n_out = job.out2 ? 2 : 1;
-    const size_t budget = resolve_budget(ex, true);
+    const size_t budget = resolve_budget(ex);
     int32_t halo[3] = {total_halo(job.stages, 0), total_halo(job.stages, 1), total_halo(job.stages, 2)};
     const int64_t zero[3] = {0, 0, 0};
     ChunkCost cost{true, in_es, out_es, n_out, &job.stages};
@@ -493,6 +497,13 @@ void run_host(const Job &job, Mem min, Mem mout, harpia_stats *stats)
 
     StreamH s_h2d, s_comp, s_d2h;
     std::vector<EventH> ev_h2d(NB), ev_comp(NB), ev_d2h(NB);
+    // With stats: timing events around each chunk's kernels on the compute
+    // stream (their sum is the kernel time of the streamed run).
+    std::vector<std::unique_ptr<EventH>> ev_k;
+    if (stats) {
+        ev_k.reserve((size_t)(2 * p.n_chunks));
+        for (int64_t i = 0; i < 2 * p.n_chunks; ++i) ev_k.emplace_back(new EventH(true));
+    }
     std::vector<int64_t> pending(NB, -1);  // chunk whose output awaits scatter
 
     int64_t bytes_h2d = 0, bytes_d2h = 0;
@@ -544,8 +555,10 @@ void run_host(const Job &job, Mem min, Mem mout, harpia_stats *stats)
         const Region rout = dense_region(S.out, c0, c1);
         Region rout2;
         if (n_out > 1) rout2 = dense_region(S.out2, c0, c1);
+        if (stats) check_hip(hipEventRecord(ev_k[2 * i]->e, s_comp.s), "hipEventRecord");
         run_chunk_stages(job, rin, rout, n_out > 1 ? &rout2 : nullptr, c0, c1, S.inter.data(), S.scratch, scratch,
                          s_comp.s);
+        if (stats) check_hip(hipEventRecord(ev_k[2 * i + 1]->e, s_comp.s), "hipEventRecord");
         check_hip(hipEventRecord(ev_comp[b].e, s_comp.s), "hipEventRecord");
 
         // D2H of the core.
@@ -569,6 +582,13 @@ void run_host(const Job &job, Mem min, Mem mout, harpia_stats *stats)
     check_hip(hipStreamSynchronize(s_comp.s), "hipStreamSynchronize");
     check_hip(hipStreamSynchronize(s_d2h.s), "hipStreamSynchronize");
     if (stats) {
+        double kms = 0.0;
+        for (int64_t i = 0; i < p.n_chunks; ++i) {
+            float t = 0.f;
+            check_hip(hipEventElapsedTime(&t, ev_k[2 * i]->e, ev_k[2 * i + 1]->e), "hipEventElapsedTime");
+            kms += t;
+        }
+        stats->kernel_ms = kms;
         stats->n_chunks = p.n_chunks;
         stats->bytes_h2d = bytes_h2d;
         stats->bytes_d2h = bytes_d2h;
@@ -670,19 +690,33 @@ void plan_chunks(const int64_t n[3], const int32_t halo[3], const int64_t chunk[
     p.budget_bytes = budget;
 }
 
-size_t resolve_budget(const harpia_exec *ex, bool need_device)
+size_t resolve_budget(const harpia_exec *ex)
 {
-    const char *env_b = std::getenv("HARPIA_DEVICE_BUDGET");
-    if (env_b && *env_b) return (size_t)std::strtoull(env_b, nullptr, 10);
-    if (ex && ex->device_budget_bytes) return ex->device_budget_bytes;
-    double frac = (ex && ex->budget_fraction > 0) ? ex->budget_fraction : HARPIA_DEFAULT_BUDGET_FRACTION;
-    const char *env_f = std::getenv("HARPIA_BUDGET_FRACTION");
-    if (env_f && *env_f) frac = std::atof(env_f);
+    // cap: the caller's, else the environment's default, else none
+    size_t cap = ex ? ex->device_budget_bytes : 0;
+    if (!cap) {
+        const char *env_b = std::getenv("HARPIA_DEVICE_BUDGET");
+        if (env_b && *env_b) cap = (size_t)std::strtoull(env_b, nullptr, 10);
+    }
+    double frac = HARPIA_DEFAULT_BUDGET_FRACTION;
+    if (ex && ex->budget_fraction > 0) {
+        frac = ex->budget_fraction;
+    } else {
+        const char *env_f = std::getenv("HARPIA_BUDGET_FRACTION");
+        if (env_f && *env_f) frac = std::atof(env_f);
+    }
     if (!(frac > 0.0 && frac <= 1.0)) fail(HARPIA_ERR_ARG, "budget fraction must be in (0, 1]");
-    if (!need_device) fail(HARPIA_ERR_ARG, "an explicit device budget is needed without a device");
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev < 1) {
+        (void)hipGetLastError();
+        // no device to query: a plan-only call keeps the cap as given
+        if (cap) return cap;
+        fail(HARPIA_ERR_ARG, "an explicit device budget is needed without a device");
+    }
     size_t free_b = 0, total_b = 0;
     check_hip(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-    return (size_t)((double)free_b * frac);
+    const size_t limit = (size_t)((double)free_b * frac);
+    return cap ? std::min(cap, limit) : limit;
 }
 
 bool is_device_pointer(const void *ptr) { return classify(ptr) == Mem::Device; }

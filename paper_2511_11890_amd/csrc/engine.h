@@ -47,10 +47,14 @@ size_t chunk_bytes(const ChunkCost &c, const int64_t core[3], const int64_t n[3]
 void plan_chunks(const int64_t n[3], const int32_t halo[3], const int64_t chunk[3], const ChunkCost &cost,
                  size_t budget, int max_buffers, harpia_plan &p);
 
-// Device budget in bytes: explicit cap, else fraction x free device memory
-// (Section III-D, step 1).  Environment overrides: HARPIA_DEVICE_BUDGET
-// (bytes), HARPIA_BUDGET_FRACTION.
-size_t resolve_budget(const harpia_exec *ex, bool need_device);
+// Device budget in bytes (Section III-D, step 1: free device memory is
+// queried and a fixed fraction of it is reserved):
+//   budget = min(cap, fraction x free), or fraction x free without a cap.
+// cap = ex->device_budget_bytes, else HARPIA_DEVICE_BUDGET (bytes) as the
+// default of callers that give none; fraction = ex->budget_fraction, else
+// HARPIA_BUDGET_FRACTION, else HARPIA_DEFAULT_BUDGET_FRACTION.  Without a
+// device (plan-only calls) the cap is returned unclipped.
+size_t resolve_budget(const harpia_exec *ex);
 
 // Device memory owned for the duration of one call (freed by the
 // destructor).  alloc() honours the HARPIA_TEST_FAIL_ALLOC_AT test hook.

@@ -133,7 +133,7 @@ struct StoreOut {
 // c_{-k} = -c_k and c_0 = 0, with w[k] = c_k for k >= 1 (a first-derivative
 // correlation, v[i + k] weighted by c_k); even taps otherwise.
 template <typename Tin, int R, int D, class Out, int PAR = 0, int TX = kTX>
-__device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const GaussTaps &taps, int zlen, int bx, int by,
+__device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const FusedTaps &taps, int zlen, int bx, int by,
                                            int bz, int rot, Out &out)
 {
     constexpr int NT = TX / 4 * kTY;  // threads: one 4-column quad each
@@ -367,8 +367,8 @@ __device__ __forceinline__ float block_sum_256(float v)
 // x and g are dense [nz][ny][nx] volumes; g is float.  Adds this thread's
 // share of S_z, S_y, S_x over slices [zo0, zo1) of the tile to sum[3].
 template <typename Tin, int R, int D>
-__device__ __forceinline__ void sigma3_tile(const Tin *x, const float *g, const int64_t n[3], const GaussTaps &wt,
-                                            const GaussTaps &dt, int64_t x0, int64_t y0, int64_t zo0, int64_t zo1,
+__device__ __forceinline__ void sigma3_tile(const Tin *x, const float *g, const int64_t n[3], const FusedTaps &wt,
+                                            const FusedTaps &dt, int64_t x0, int64_t y0, int64_t zo0, int64_t zo1,
                                             float sum[3])
 {
     constexpr int P = 2 * R + 1;
@@ -541,7 +541,7 @@ __device__ __forceinline__ void sigma3_tile(const Tin *x, const float *g, const 
 // partials[stride + b], partials[2 stride + b] get its S_z, S_y, S_x.
 template <typename Tin, int R, int D = gauss_prefetch_depth(R)>
 __global__ __launch_bounds__(kNT) void gauss_sigma3_kernel(const Tin *x, const float *g, int64_t nz, int64_t ny,
-                                                           int64_t nx, GaussTaps wt, GaussTaps dt, int zlen,
+                                                           int64_t nx, FusedTaps wt, FusedTaps dt, int zlen,
                                                            int tiles_x, int tiles_y, float *partials, int64_t stride)
 {
     const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(kNT) void gauss_sigma3_kernel(const Tin *x, const f
 // Batched: persistent over the (crop, tile, z range) items; in = x, out =
 // upstream gradient g.  One partial per workgroup and axis.
 template <typename Tin, int R, int D = gauss_prefetch_depth(R)>
-__global__ __launch_bounds__(kNT) void gauss_sigma3_batched_kernel(BatchDesc d, GaussTaps wt, GaussTaps dt,
+__global__ __launch_bounds__(kNT) void gauss_sigma3_batched_kernel(BatchDesc d, FusedTaps wt, FusedTaps dt,
                                                                    float *partials, int64_t stride)
 {
     const int total = d.prefix[d.n_crops];
@@ -591,7 +591,7 @@ __device__ __forceinline__ void tile_of_block(uint32_t b, int tiles_x, int tiles
 }
 
 template <typename Tin, typename Tout, int R, bool UNSHARP = false, int PAR = 0, int D = gauss_prefetch_depth(R)>
-__global__ __launch_bounds__(fused_tx(R) / 4 * kTY) void gauss_fused_kernel(ChunkArgs a, GaussTaps taps, int zlen,
+__global__ __launch_bounds__(fused_tx(R) / 4 * kTY) void gauss_fused_kernel(ChunkArgs a, FusedTaps taps, int zlen,
                                                                           int tiles_x, int tiles_y)
 {
     int bx, by, bz;
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(fused_tx(R) / 4 * kTY) void gauss_fused_kernel(Chun
 // xcd_remap(b) + k * gridDim (so the workgroups of one XCD hold neighbouring
 // tiles at any time); the LDS of the tile routine is reused between items.
 template <typename Tin, typename Tout, int R, int D = gauss_prefetch_depth(R)>
-__global__ __launch_bounds__(kNT) void gauss_batched_kernel(BatchDesc d, GaussTaps taps)
+__global__ __launch_bounds__(kNT) void gauss_batched_kernel(BatchDesc d, FusedTaps taps)
 {
     const int total = d.prefix[d.n_crops];
     for (int w = (int)xcd_remap(blockIdx.x, gridDim.x); w < total; w += gridDim.x) {
@@ -659,7 +659,7 @@ void launch_fused_u(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
     const bool tuned = tune_lookup(TF_GAUSS, tune_key_volume(TF_GAUSS, R, code, a.out_e), t);
     const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0, fused_tx(R));
     hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R, UNSHARP, PAR>), dim3((uint32_t)g.blocks), dim3(NT), 0, s,
-                       a, taps, g.zlen, g.tiles_x, g.tiles_y);
+                       a, fused_taps(taps), g.zlen, g.tiles_x, g.tiles_y);
 }
 
 // Odd taps (derivative filters: the mixed Hessian components) are built for
@@ -778,7 +778,8 @@ void launch_batched(BatchDesc d, const GaussTaps &taps, hipStream_t s)
     batch_layout(d, kTX, kTY, tuned && t.tz > 0 ? t.tz : kBatchZ);
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < kBatchMaxGrid ? cap : kBatchMaxGrid);
     if (grid > 0)
-        hipLaunchKernelGGL((gauss_batched_kernel<Tin, Tout, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, taps);
+        hipLaunchKernelGGL((gauss_batched_kernel<Tin, Tout, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d,
+                           fused_taps(taps));
 }
 
 template <typename Tin, typename Tout>
@@ -844,7 +845,7 @@ int64_t launch_sigma3(const Tin *x, const float *g, const int64_t n[3], const Ga
     const int zlen = sigma3_zlen(n[0], tiles, cap, tuned ? t.tz : 0);
     const int64_t blocks = tiles * ((n[0] + zlen - 1) / zlen);
     hipLaunchKernelGGL((gauss_sigma3_kernel<Tin, R>), dim3((uint32_t)blocks), dim3(kNT), 0, s, x, g, n[0], n[1],
-                       n[2], wt, dt, zlen, tiles_x, tiles_y, partials, blocks);
+                       n[2], fused_taps(wt), fused_taps(dt), zlen, tiles_x, tiles_y, partials, blocks);
     return blocks;
 }
 
@@ -858,8 +859,8 @@ int64_t launch_sigma3_batched(BatchDesc d, const GaussTaps &wt, const GaussTaps 
     batch_layout(d, kTX, kTY, tuned && t.tz > 0 ? t.tz : kBatchZ);
     const int64_t grid = batch_grid(d.prefix[d.n_crops], cap < kBatchMaxGrid ? cap : kBatchMaxGrid);
     if (grid > 0)
-        hipLaunchKernelGGL((gauss_sigma3_batched_kernel<Tin, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d, wt, dt,
-                           partials, grid);
+        hipLaunchKernelGGL((gauss_sigma3_batched_kernel<Tin, R>), dim3((uint32_t)grid), dim3(kNT), 0, s, d,
+                           fused_taps(wt), fused_taps(dt), partials, grid);
     return grid;
 }
 

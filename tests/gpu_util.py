@@ -76,3 +76,22 @@ def sample_points(shape, n, seed=0, r=0):
     while len(pts) < n:
         pts.add(tuple(int(rng.integers(0, s)) for s in shape))
     return sorted(pts)
+
+
+def fp32_gauss_rel_bound(r: int) -> float:
+    """Worst-case relative error of an FP32 separable Gaussian of radius r
+    against FP64: three passes of 2r+1 products and sums with taps rounded
+    to FP32, each step within 2^-24 of its exact value, scaled by G(|x|)."""
+    return 3 * (2 * r + 1) * 2.0 ** -24
+
+
+def near_ties(y64: np.ndarray, r: int, rel: float) -> np.ndarray:
+    """Voxels whose box-(2r+1) window (offsets outside the volume skipped)
+    has its top two values within rel * max|y|.  With rel twice the error
+    bound of the values y, an FP32 and an FP64 argmax can differ only at
+    these voxels; everywhere else the routing is unique."""
+    from numpy.lib.stride_tricks import sliding_window_view
+    p = np.pad(y64, r, mode="constant", constant_values=-np.inf)
+    w = sliding_window_view(p, (2 * r + 1,) * 3).reshape(y64.shape + (-1,))
+    top2 = -np.partition(-w, 1, axis=-1)[..., :2]
+    return (top2[..., 0] - top2[..., 1]) <= rel * np.max(np.abs(y64))

@@ -165,3 +165,24 @@ def test_plan_paper_config_brick_counts():
     assert p.n_chunks == 64
     per_set = math.ceil(524 ** 3 * 2 / 256) * 256 + 512 ** 3 * 4
     assert p.device_bytes == p.n_buffers * per_set
+
+
+def _plain_host() -> bool:
+    try:
+        import torch
+        return not torch.cuda.is_available()
+    except Exception:
+        return True
+
+
+@pytest.mark.skipif(not _plain_host(), reason="the unclipped cap is the no-device case")
+def test_budget_env_is_only_a_default(monkeypatch):
+    # Section III-D, step 1: the caller's cap wins over the environment's
+    # default; with no cap given, the environment's cap is used.
+    monkeypatch.setenv("HARPIA_DEVICE_BUDGET", str(3 << 20))
+    p = h.plan((64, 64, 64), "f32", "f32", (1, 1, 1), budget=5 << 20)
+    assert p.budget_bytes == 5 << 20
+    p = h.plan((64, 64, 64), "f32", "f32", (1, 1, 1))
+    assert p.budget_bytes == 3 << 20
+    monkeypatch.delenv("HARPIA_DEVICE_BUDGET")
+    assert _status(lambda: h.plan((64, 64, 64), "f32", "f32", (1, 1, 1))) == _lib.HARPIA_ERR_ARG

@@ -10,7 +10,7 @@ import torch
 import oracle
 import paper_2511_11890_amd as h
 from paper_2511_11890_amd import phantoms
-from tests.gpu_util import FP32_GAUSS_TOL, gauss_scale, to_np64
+from tests.gpu_util import FP32_GAUSS_TOL, fp32_gauss_rel_bound, gauss_scale, near_ties, to_np64
 
 pytestmark = pytest.mark.gpu
 
@@ -64,6 +64,30 @@ def test_sigma_gradient_host_pointer_and_deterministic(dev):
         x.data_ptr(), h._lib.HARPIA_F32, g.data_ptr(), None, h._lib.i64_3(shape), h._lib.f64_3((2.0,) * 3),
         h._lib.i32_3((6, 6, 6)), out.ctypes.data, h._lib.make_exec(stream=torch.cuda.current_stream().cuda_stream)))
     np.testing.assert_array_equal(out, a.cpu().numpy())
+
+
+@pytest.mark.parametrize("sigma,r", [(2.0, (6, 6, 6)), ((1.0, 1.5, 2.0), (3, 5, 6))])
+def test_sigma_gradient_sum_flag(dev, sigma, r):
+    # HARPIA_F_SIGMA_SUM: one FP64 value, the sum of the three axis terms,
+    # into a device pointer and (through the raw C ABI) a host pointer; the
+    # unfused path (unequal radii) sums its per-axis reductions
+    shape = (22, 37, 90)
+    x = phantoms.porous(shape, seed=45).to(dev)
+    g = phantoms.gaussian_noise(shape, seed=46).to(dev)
+    _, g3 = h.gaussian_backward(x, g, sigma, r, grad_in=False)
+    _, g1 = h.gaussian_backward(x, g, sigma, r, grad_in=False, sigma_sum=True)
+    torch.cuda.synchronize()
+    assert g1.shape == (1,)
+    want = float(g3.sum())
+    assert abs(float(g1[0]) - want) <= 1e-12 * float(g3.abs().sum())
+    out = np.full(3, 7.0)
+    lib = h._lib.load()
+    h._lib.check(lib.harpia_gaussian3d_backward(
+        x.data_ptr(), h._lib.HARPIA_F32, g.data_ptr(), None, h._lib.i64_3(shape),
+        h._lib.f64_3(h._triple(sigma, float)), h._lib.i32_3(r), out.ctypes.data,
+        h._lib.make_exec(stream=torch.cuda.current_stream().cuda_stream, flags=h._lib.HARPIA_F_SIGMA_SUM)))
+    assert out[0] == float(g1[0])
+    assert out[1] == 7.0 and out[2] == 7.0  # one value written
 
 
 @pytest.mark.parametrize("op", ["erode", "dilate"])
@@ -121,27 +145,21 @@ def test_morph_gradient_dtypes(dev, dtype):
     assert np.all(np.abs(to_np64(gi) - want) <= 125 * 2.0 ** -24 * mag)
 
 
-def _near_ties(y64, r, rel):
-    """Voxels whose box-(2r+1) window has its top two values within
-    rel * max|y| (the FP32 and FP64 argmax may legitimately differ there)."""
-    from numpy.lib.stride_tricks import sliding_window_view
-    p = np.pad(y64, r, mode="constant", constant_values=-np.inf)
-    w = sliding_window_view(p, (2 * r + 1,) * 3).reshape(y64.shape + (-1,))
-    top2 = -np.partition(-w, 1, axis=-1)[..., :2]
-    return (top2[..., 0] - top2[..., 1]) <= rel * np.max(np.abs(y64))
-
-
 def test_composite_loss_gradient_vs_oracle(dev):
     """L = sum c * dilate_box5(G_sigma x), sigma = 1.5 (r = 5): input and sigma
     gradients from GaussDilateFn against the FP64 oracle.  Outputs whose
-    dilation window has a near-tie (FP32 vs FP64 may pick different maxima)
-    are masked out of c; they must be rare."""
+    dilation window has a near-tie (top-two gap within twice the FP32
+    Gaussian's error bound, where FP32 and FP64 may pick different maxima)
+    are masked out of c.  Their share is a property of the input (a smooth
+    field has near-equal neighbours around each local maximum, and a maximum
+    is the window maximum of up to 125 outputs): 0.27% here; the bound only
+    keeps the mask from swallowing the check."""
     shape = (30, 41, 96)
     x = phantoms.porous(shape, seed=39)
     c = phantoms.gaussian_noise(shape, seed=40)
     y64 = oracle.gaussian3d(to_np64(x), 1.5, method="separable")
-    ties = _near_ties(y64, 2, 1e-5)
-    assert ties.mean() < 1e-2
+    ties = near_ties(y64, 2, 2 * fp32_gauss_rel_bound(5))
+    assert ties.mean() < 5e-3
     c[torch.from_numpy(ties)] = 0.0
     xd = x.to(dev).requires_grad_(True)
     sig = torch.tensor(1.5, dtype=torch.float64, requires_grad=True)
