@@ -346,6 +346,28 @@ harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t,
                                          double *grad_sigma,
                                          const harpia_exec *ex);
 
+/* harpia_gaussian3d_backward without any device allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and errors as harpia_gaussian3d_backward, restricted to the single-launch
+ * kernels: equal radii in [1, 12] and slices of fewer than 2^31 voxels
+ * (else HARPIA_ERR_UNSUPPORTED).  Its scratch -- the sigma-gradient's FP32
+ * workgroup partials and the FP64 results bound for a host grad_sigma --
+ * is a fixed 4 MiB device array of the library, one per GPU, held until
+ * the process ends; a volume whose partials exceed it (about 3 x 2^20
+ * floats: 3 per 64 x 16 column tile and z range) is rejected with
+ * HARPIA_ERR_ARG.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (several host threads or streams) race and must be
+ * serialised by the caller.  With a device grad_sigma (or none) the call is
+ * asynchronous on ex->stream; a host grad_sigma is filled before return. */
+harpia_status harpia_gaussian3d_backward_noalloc(const void *x, harpia_dtype x_t,
+                                                 const void *grad_out, void *grad_in,
+                                                 const int64_t shape[3],
+                                                 const double sigma[3],
+                                                 const int32_t radius[3],
+                                                 double *grad_sigma,
+                                                 const harpia_exec *ex);
+
 /* Subgradient of erosion (op = HARPIA_ERODE) or dilation of `in` (dtype t,
  * grayscale): every output voxel p sends grad_out[p] to the input voxel that
  * supplied its extremum, the first in lexicographic (dz, dy, dx) order over

@@ -120,6 +120,8 @@ SIGNATURES = {
                                       ctypes.c_int, _ex]),
     "harpia_gaussian3d_backward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _I64_3, _F64_3, _I32_3,
                                                   _vp, _ex]),
+    "harpia_gaussian3d_backward_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _I64_3, _F64_3, _I32_3,
+                                                          _vp, _ex]),
     "harpia_morph3d_backward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _I64_3, ctypes.c_int,
                                                ctypes.c_int, _I32_3, _ex]),
     "harpia_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(harpia_crop), ctypes.c_int32]),

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -615,6 +616,117 @@ harpia_status harpia_gaussian3d_backward(const void *x, harpia_dtype x_t, const 
             allocated = true;
         }
         if (allocated) check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    });
+}
+
+}  // extern "C"
+
+namespace harpia {
+namespace {
+
+// Device scratch of harpia_gaussian3d_backward_noalloc: a 256-byte header
+// for the sigma-gradient values (host destinations are copied from there)
+// followed by the FP32 workgroup partials of the sigma-gradient kernel.
+// Each GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` only names the symbol: its device address comes
+// from hipGetSymbolAddress, looked up once per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)4 << 20;
+constexpr size_t kNoAllocHeaderBytes = 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxScratchDevices = 256;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxScratchDevices];
+
+// Device address of the current device's copy of `scratch`.
+unsigned char *device_scratch()
+{
+    int dev = -1;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices) fail(HARPIA_ERR_UNSUPPORTED, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    return static_cast<unsigned char *>(g_scratch_ptr[dev]);
+}
+
+}  // namespace
+}  // namespace harpia
+
+extern "C" {
+
+harpia_status harpia_gaussian3d_backward_noalloc(const void *x, harpia_dtype x_t, const void *grad_out,
+                                                 void *grad_in, const int64_t shape[3], const double sigma[3],
+                                                 const int32_t radius[3], double *grad_sigma, const harpia_exec *ex)
+{
+    return guarded([&] {
+        check_shape(shape);
+        check_exec(ex);
+        if (!grad_out) fail(HARPIA_ERR_ARG, "grad_out is NULL");
+        if (!sigma || !radius) fail(HARPIA_ERR_ARG, "sigma / radius is NULL");
+        for (int a = 0; a < 3; ++a) {
+            if (!(sigma[a] > 0.0) || !std::isfinite(sigma[a])) fail(HARPIA_ERR_ARG, "sigma must be finite and > 0");
+            if (radius[a] < 0 || radius[a] > kMaxGaussRadius)
+                fail(HARPIA_ERR_ARG, "radius must be in [0, " + std::to_string(kMaxGaussRadius) + "]");
+        }
+        if (grad_sigma && !x) fail(HARPIA_ERR_ARG, "x is NULL (needed for grad_sigma)");
+        if (grad_sigma && !valid_dtype(x_t)) fail(HARPIA_ERR_DTYPE, "unsupported dtype");
+        if (!grad_in && !grad_sigma) return;
+        const int64_t nv = voxels(shape);
+        if (grad_in) check_alias(grad_out, nv * 4, grad_in, nv * 4);
+        if (grad_in && x) check_alias(x, nv * dtype_size(x_t), grad_in, nv * 4);
+        reset_alloc_counter();  // the test hook then fails any allocation of this call
+        if (!is_device_pointer(grad_out) || (grad_in && !is_device_pointer(grad_in)) ||
+            (grad_sigma && !is_device_pointer(x)))
+            fail(HARPIA_ERR_UNSUPPORTED, "the backward runs on device-resident volumes");
+        const int r[3] = {radius[0], radius[1], radius[2]};
+        // only the single-launch kernels, which need no scratch volume
+        if (!(r[0] == r[1] && r[1] == r[2] && r[0] >= 1 && r[0] <= kGaussFusedMaxR) ||
+            shape[1] * shape[2] >= ((int64_t)1 << 31) || !gauss_slices_fit(shape))
+            fail(HARPIA_ERR_UNSUPPORTED, "the no-allocation backward needs equal radii in [1, " +
+                                             std::to_string(kGaussFusedMaxR) + "] and slices of < 2^31 voxels");
+        const size_t part_bytes = (size_t)(3 * gauss_sigma3_blocks_bound(shape)) * sizeof(float);
+        if (grad_sigma && kNoAllocHeaderBytes + part_bytes > kNoAllocScratchBytes)
+            fail(HARPIA_ERR_ARG, "volume too large for the no-allocation scratch: " + std::to_string(part_bytes) +
+                                     " bytes of partials, at most " +
+                                     std::to_string(kNoAllocScratchBytes - kNoAllocHeaderBytes));
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        unsigned char *base = grad_sigma ? device_scratch() : nullptr;
+        if (grad_in) {
+            GaussTaps taps;
+            make_gauss_taps_r(sigma, r, taps);
+            const ChunkArgs a = make_chunk_args(whole_region(grad_out, shape), whole_region(grad_in, shape), shape);
+            if (!launch_gaussian(a, HARPIA_F32, HARPIA_F32, taps, s, nullptr, 0))
+                fail(HARPIA_ERR_UNSUPPORTED, "no fused Gaussian kernel for these radii");
+            check_hip(hipGetLastError(), "kernel launch");
+        }
+        if (grad_sigma) {
+            const bool sum = ex && (ex->flags & HARPIA_F_SIGMA_SUM);
+            const int n_sig = sum ? 1 : 3;
+            const bool dev_out = is_device_pointer(grad_sigma);
+            double *dst = dev_out ? grad_sigma : reinterpret_cast<double *>(base);
+            float *part = reinterpret_cast<float *>(base + kNoAllocHeaderBytes);
+            GaussTaps wt3, dt3;
+            make_gauss_taps_r(sigma, r, wt3);
+            make_gauss_dtaps3(sigma, r, dt3);
+            // every partial the reduction reads is written by this launch
+            const int64_t nb = launch_gauss_sigma3(x, x_t, static_cast<const float *>(grad_out), shape, wt3, dt3, s,
+                                                   part);
+            if (nb < 0) fail(HARPIA_ERR_UNSUPPORTED, "no fused sigma-gradient kernel for these radii");
+            check_hip(hipGetLastError(), "kernel launch");
+            for (int axis = 0; axis < n_sig; ++axis) {
+                launch_reduce_f64(part + axis * nb, sum ? 3 * nb : nb, dst + axis, false, s);
+                check_hip(hipGetLastError(), "kernel launch");
+            }
+            if (!dev_out) {
+                check_hip(hipMemcpyAsync(grad_sigma, dst, n_sig * sizeof(double), hipMemcpyDeviceToHost, s),
+                          "hipMemcpyAsync");
+                check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+            }
+        }
     });
 }
 
