@@ -89,6 +89,11 @@ typedef enum harpia_morph_op { HARPIA_ERODE = 0, HARPIA_DILATE = 1 } harpia_morp
                                        one double, the sum of the three axis
                                        terms (the gradient of an isotropic
                                        sigma), reduced on the device in FP64 */
+#define HARPIA_F_REUSE_CODES 0x8u   /* batched morphology backward: take the
+                                       extremum codes that
+                                       harpia_morph3d_forward_batched left in
+                                       the workspace instead of recomputing
+                                       them from the forward input */
 
 /* Optional per-call statistics (filled when harpia_exec.stats != NULL). */
 typedef struct harpia_stats {
@@ -433,9 +438,27 @@ harpia_status harpia_gaussian3d_backward_batched(const harpia_crop *crops,
                                                  size_t workspace_bytes,
                                                  const harpia_exec *ex);
 
+/* Erosion / dilation of every crop (in -> out, float32, as
+ * harpia_morph3d_batched) from the same pass that records, per output voxel,
+ * the code of the offset that supplied its extremum (the first in
+ * lexicographic (dz, dy, dx) order, as harpia_morph3d_backward routes) into
+ * `workspace` (harpia_batch_workspace_bytes of these crops).  A later
+ * harpia_morph3d_backward_batched on the same crops, element and workspace
+ * with HARPIA_F_REUSE_CODES takes them instead of recomputing them, so the
+ * forward input need not be kept.  Box radii up to 8, ball radius up to 4. */
+harpia_status harpia_morph3d_forward_batched(const harpia_crop *crops,
+                                             int32_t n_crops,
+                                             harpia_morph_op op, harpia_se se,
+                                             const int32_t radius[3],
+                                             void *workspace,
+                                             size_t workspace_bytes,
+                                             const harpia_exec *ex);
+
 /* Erosion / dilation subgradient over a batch: per crop in = forward input,
  * aux = grad_out, out = grad_in; rules of harpia_morph3d_backward.  The
- * codes live in `workspace` (harpia_batch_workspace_bytes). */
+ * codes live in `workspace` (harpia_batch_workspace_bytes); with
+ * HARPIA_F_REUSE_CODES they are taken from a preceding
+ * harpia_morph3d_forward_batched and `in` may be NULL. */
 harpia_status harpia_morph3d_backward_batched(const harpia_crop *crops,
                                               int32_t n_crops,
                                               harpia_morph_op op, harpia_se se,

@@ -566,12 +566,14 @@ class GaussDilateBatch:
     allocated up front so that a step allocates nothing and can be captured
     in a CUDA/HIP graph:
 
-        fwd:  y = G x (batched), d = dilate(y) (batched)
-        bwd:  y = G x recomputed, g_y = routed g_d (argext + gather, batched),
+        fwd:  y = G x (batched), d = dilate(y) with the codes of the maxima
+              kept in the workspace (one batched pass)
+        bwd:  g_y = g_d routed through the kept codes (batched gather),
               g_x = G g_y (batched), d L / d sigma = sum_a <g_y, G'_a x>
               (batched dot, FP64 reduction, the three axis terms summed
               on the device) -- kept on the device.
-    sigma is a Python float (isotropic); its radius is resolved once."""
+    Six launches per step.  sigma is a Python float (isotropic); its radius
+    is resolved once."""
 
     def __init__(self, xs, sigma: float, se: str = "box", radius=2, truncate: float = 3.0):
         torch = _torch()
@@ -596,30 +598,30 @@ class GaussDilateBatch:
         s3 = _lib.f64_3((self.sigma,) * 3)
         _lib.check(lib.harpia_gaussian3d_batched(self._c_fwd_g, n, _lib.HARPIA_F32, _lib.HARPIA_F32, s3,
                                                  self.truncate, st))
-        _lib.check(lib.harpia_morph3d_batched(self._c_fwd_d, n, _lib.HARPIA_F32, _lib.HARPIA_DILATE,
-                                              {"box": 0, "ball": 1}[self.se], _lib.i32_3(_triple(self.mr, int)),
-                                              st))
+        _lib.check(lib.harpia_morph3d_forward_batched(self._c_fwd_d, n, _lib.HARPIA_DILATE,
+                                                      {"box": 0, "ball": 1}[self.se],
+                                                      _lib.i32_3(_triple(self.mr, int)), self.workspace.data_ptr(),
+                                                      self.workspace.numel(), st))
         return self.ds
 
     def backward(self, gds):
         """gds: upstream gradients (float32 tensors like the crops).  Returns
         (grad_x list, dL/dsigma of the isotropic sigma as a float64 device
         tensor [1])."""
-        lib, n, st = _lib.load(), len(self.xs), _lib.make_exec(stream=_stream())
+        lib, n = _lib.load(), len(self.xs)
         st_sum = _lib.make_exec(stream=_stream(), flags=_lib.HARPIA_F_SIGMA_SUM)
+        st_reuse = _lib.make_exec(stream=_stream(), flags=_lib.HARPIA_F_REUSE_CODES)
         if self.gds is not gds:
             self.gds = gds
-            self._c_bwd_m = _lib.crops([(y, gy, g) for y, gy, g in zip(self.ys, self.gys, gds)])
+            self._c_bwd_m = _lib.crops([(None, gy, g) for gy, g in zip(self.gys, gds)])
             self._c_bwd_g = _lib.crops([(x, gx, gy) for x, gx, gy in zip(self.xs, self.gxs, self.gys)])
         s3 = _lib.f64_3((self.sigma,) * 3)
         r3 = _lib.i32_3((self.r,) * 3)
         ws, wsb = self.workspace.data_ptr(), self.workspace.numel()
-        # recompute y instead of keeping it from the forward
-        _lib.check(lib.harpia_gaussian3d_batched(self._c_fwd_g, n, _lib.HARPIA_F32, _lib.HARPIA_F32, s3,
-                                                 self.truncate, st))
+        # route through the codes the forward kept (no recomputation of y)
         _lib.check(lib.harpia_morph3d_backward_batched(self._c_bwd_m, n, _lib.HARPIA_DILATE,
                                                        {"box": 0, "ball": 1}[self.se],
-                                                       _lib.i32_3(_triple(self.mr, int)), ws, wsb, st))
+                                                       _lib.i32_3(_triple(self.mr, int)), ws, wsb, st_reuse))
         _lib.check(lib.harpia_gaussian3d_backward_batched(self._c_bwd_g, n, s3, r3, self.gsigma.data_ptr(), ws,
                                                           wsb, st_sum))
         return self.gxs, self.gsigma

@@ -36,6 +36,7 @@ HARPIA_ERODE, HARPIA_DILATE = 0, 1
 HARPIA_F_BINARY = 0x1
 HARPIA_F_FORCE_CHUNKED = 0x2
 HARPIA_F_SIGMA_SUM = 0x4
+HARPIA_F_REUSE_CODES = 0x8
 
 
 class harpia_stats(ctypes.Structure):
@@ -131,6 +132,9 @@ SIGNATURES = {
                                               ctypes.c_int, ctypes.c_int, _I32_3, _ex]),
     "harpia_gaussian3d_backward_batched": (ctypes.c_int, [ctypes.POINTER(harpia_crop), ctypes.c_int32, _F64_3,
                                                           _I32_3, _vp, _vp, ctypes.c_size_t, _ex]),
+    "harpia_morph3d_forward_batched": (ctypes.c_int, [ctypes.POINTER(harpia_crop), ctypes.c_int32,
+                                                      ctypes.c_int, ctypes.c_int, _I32_3, _vp,
+                                                      ctypes.c_size_t, _ex]),
     "harpia_morph3d_backward_batched": (ctypes.c_int, [ctypes.POINTER(harpia_crop), ctypes.c_int32,
                                                        ctypes.c_int, ctypes.c_int, _I32_3, _vp,
                                                        ctypes.c_size_t, _ex]),

@@ -923,40 +923,86 @@ harpia_status harpia_gaussian3d_backward_batched(const harpia_crop *crops, int32
     });
 }
 
+// u16 extremum codes of every crop, after the sigma-gradient partials in a
+// batch workspace (layout of harpia_batch_workspace_bytes).
+static std::vector<void *> batch_codes(const harpia_crop *crops, int32_t n_crops, void *workspace)
+{
+    const int64_t launches = (n_crops + kMaxBatch - 1) / kMaxBatch;
+    size_t off = ((size_t)(3 * launches * gauss_batched_max_partials()) * sizeof(float) + 255) / 256 * 256;
+    std::vector<void *> codes(n_crops);
+    for (int32_t i = 0; i < n_crops; ++i) {
+        codes[i] = static_cast<char *>(workspace) + off;
+        const size_t v = (size_t)(crops[i].shape[0] * crops[i].shape[1] * crops[i].shape[2]);
+        off += (v * sizeof(uint16_t) + 255) / 256 * 256;
+    }
+    return codes;
+}
+
+static MorphArgs check_batch_morph(const harpia_crop *crops, int32_t n_crops, harpia_morph_op op, harpia_se se,
+                                   const int32_t radius[3], void *workspace, size_t workspace_bytes, bool need_in,
+                                   bool need_aux)
+{
+    if (op != HARPIA_ERODE && op != HARPIA_DILATE) fail(HARPIA_ERR_ARG, "unknown morphology op");
+    const MorphArgs m = check_morph(HARPIA_F32, se, radius, std::nan(""), HARPIA_BORDER_REFLECT, nullptr);
+    if (!morph_grad_supported((int)se, m.r))
+        fail(HARPIA_ERR_UNSUPPORTED, "morphology gradient: box radii above 8 or ball radius above 4");
+    check_crops(crops, n_crops, need_in, true, need_aux);
+    const size_t need = harpia_batch_workspace_bytes(crops, n_crops);
+    if (!workspace || workspace_bytes < need) fail(HARPIA_ERR_ARG, "workspace too small");
+    if (!is_device_pointer(workspace)) fail(HARPIA_ERR_ARG, "workspace must be device memory");
+    return m;
+}
+
+harpia_status harpia_morph3d_forward_batched(const harpia_crop *crops, int32_t n_crops, harpia_morph_op op,
+                                             harpia_se se, const int32_t radius[3], void *workspace,
+                                             size_t workspace_bytes, const harpia_exec *ex)
+{
+    return guarded([&] {
+        check_exec(ex);
+        const MorphArgs m = check_batch_morph(crops, n_crops, op, se, radius, workspace, workspace_bytes, true, false);
+        hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+        const std::vector<void *> codes = batch_codes(crops, n_crops, workspace);
+        for (int32_t f = 0; f < n_crops; f += kMaxBatch) {
+            const int32_t cnt = std::min<int32_t>(kMaxBatch, n_crops - f);
+            // one pass: out = the extremum, aux = its code
+            BatchDesc d = make_desc(crops, f, cnt, 0);
+            for (int32_t i = 0; i < cnt; ++i) d.c[i].aux = codes[f + i];
+            if (!launch_argext_batched(d, HARPIA_F32, (int)op, (int)se, m.r, s))
+                fail(HARPIA_ERR_UNSUPPORTED, "no batched argext kernel");
+            check_hip(hipGetLastError(), "kernel launch");
+        }
+    });
+}
+
 harpia_status harpia_morph3d_backward_batched(const harpia_crop *crops, int32_t n_crops, harpia_morph_op op,
                                               harpia_se se, const int32_t radius[3], void *workspace,
                                               size_t workspace_bytes, const harpia_exec *ex)
 {
     return guarded([&] {
         check_exec(ex);
-        if (op != HARPIA_ERODE && op != HARPIA_DILATE) fail(HARPIA_ERR_ARG, "unknown morphology op");
-        const MorphArgs m = check_morph(HARPIA_F32, se, radius, std::nan(""), HARPIA_BORDER_REFLECT, nullptr);
-        if (!morph_grad_supported((int)se, m.r))
-            fail(HARPIA_ERR_UNSUPPORTED, "morphology gradient: box radii above 8 or ball radius above 4");
-        check_crops(crops, n_crops, true, true, true);
-        const size_t need = harpia_batch_workspace_bytes(crops, n_crops);
-        if (!workspace || workspace_bytes < need) fail(HARPIA_ERR_ARG, "workspace too small");
-        if (!is_device_pointer(workspace)) fail(HARPIA_ERR_ARG, "workspace must be device memory");
+        const bool reuse = ex && (ex->flags & HARPIA_F_REUSE_CODES);
+        const MorphArgs m = check_batch_morph(crops, n_crops, op, se, radius, workspace, workspace_bytes, !reuse, true);
         hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
-        // codes live after the sigma-gradient partials
-        const int64_t launches = (n_crops + kMaxBatch - 1) / kMaxBatch;
-        size_t off = ((size_t)(3 * launches * gauss_batched_max_partials()) * sizeof(float) + 255) / 256 * 256;
-        std::vector<void *> codes(n_crops);
-        for (int32_t i = 0; i < n_crops; ++i) {
-            codes[i] = static_cast<char *>(workspace) + off;
-            const size_t v = (size_t)(crops[i].shape[0] * crops[i].shape[1] * crops[i].shape[2]);
-            off += (v * sizeof(uint16_t) + 255) / 256 * 256;
-        }
+        const std::vector<void *> codes = batch_codes(crops, n_crops, workspace);
         for (int32_t f = 0; f < n_crops; f += kMaxBatch) {
             const int32_t cnt = std::min<int32_t>(kMaxBatch, n_crops - f);
             BatchDesc d = make_desc(crops, f, cnt, 0);
-            // argext: in = forward input, aux = codes
-            for (int32_t i = 0; i < cnt; ++i) d.c[i].aux = codes[f + i];
-            if (!launch_argext_batched(d, HARPIA_F32, (int)op, (int)se, m.r, s))
-                fail(HARPIA_ERR_UNSUPPORTED, "no batched argext kernel");
-            check_hip(hipGetLastError(), "kernel launch");
+            if (!reuse) {
+                // argext: in = forward input, aux = codes (no values)
+                for (int32_t i = 0; i < cnt; ++i) {
+                    d.c[i].aux = codes[f + i];
+                    d.c[i].out = nullptr;
+                }
+                if (!launch_argext_batched(d, HARPIA_F32, (int)op, (int)se, m.r, s))
+                    fail(HARPIA_ERR_UNSUPPORTED, "no batched argext kernel");
+                check_hip(hipGetLastError(), "kernel launch");
+            }
             // gather: in = upstream gradient, aux = codes, out = grad_in
-            for (int32_t i = 0; i < cnt; ++i) d.c[i].in = crops[f + i].aux;
+            for (int32_t i = 0; i < cnt; ++i) {
+                d.c[i].in = crops[f + i].aux;
+                d.c[i].aux = codes[f + i];
+                d.c[i].out = crops[f + i].out;
+            }
             if (!launch_gather_batched(d, (int)se, m.r, s)) fail(HARPIA_ERR_UNSUPPORTED, "no batched gather kernel");
             check_hip(hipGetLastError(), "kernel launch");
         }

@@ -12,11 +12,13 @@ namespace gauss_detail {
 constexpr int kTX = 64;  // tile columns (x)
 constexpr int kTY = 16;  // tile rows (y)
 
-// Tile width of the plain fused Gaussian: 128 columns (512 threads) for
-// radii up to 6, so a patch row spans fewer partial 128-byte lines per
-// output; 64 columns (256 threads) above, where the register ring and the
-// LDS patch grow with r.
-constexpr int fused_tx(int r) { return r <= 6 ? 128 : 64; }
+// Tile width of the plain fused Gaussian: 256 columns (1024 threads) for
+// radii up to 4, 128 columns (512 threads) above.  Wider tiles stage fewer
+// x-halo columns per output (the y pass filters TX + 2r columns) and span
+// fewer partial 128-byte lines per patch row; at radius 5 and up a
+// 1024-thread workgroup's 128-register cap would spill the z ring (at
+// radius 4 already with the unsharp epilogue's extra registers).
+constexpr int fused_tx(int r, bool unsharp = false) { return r <= (unsharp ? 3 : 4) ? 256 : 128; }
 
 struct FusedGrid {
     int tiles_x, tiles_y, zlen;

@@ -6,8 +6,8 @@
 // with half-sample reflection R and normalised sampled taps (FP64 -> FP32).
 //
 // Fused kernel (equal radius r on all axes, 1 <= r <= kGaussFusedMaxR):
-//   one workgroup owns a TX x 16 tile of output columns (TX = 128 with 512
-//   threads for r <= 6, TX = 64 with 256 threads above; one 4-column quad
+//   one workgroup owns a TX x 16 tile of output columns (TX = 256 with 1024
+//   threads for r <= 4, TX = 128 with 512 threads above; one 4-column quad
 //   per thread) and streams along z over a range of output slices.  Per
 //   input slice it
 //     1. stages the (TX+2r) x (16+2r) patch in LDS (reflection applied on
@@ -591,15 +591,16 @@ __device__ __forceinline__ void tile_of_block(uint32_t b, int tiles_x, int tiles
 }
 
 template <typename Tin, typename Tout, int R, bool UNSHARP = false, int PAR = 0, int D = gauss_prefetch_depth(R)>
-__global__ __launch_bounds__(fused_tx(R) / 4 * kTY) void gauss_fused_kernel(ChunkArgs a, FusedTaps taps, int zlen,
-                                                                          int tiles_x, int tiles_y)
+__global__ __launch_bounds__(fused_tx(R, UNSHARP) / 4 * kTY) void gauss_fused_kernel(ChunkArgs a, FusedTaps taps,
+                                                                                   int zlen, int tiles_x,
+                                                                                   int tiles_y)
 {
     int bx, by, bz;
     const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
     tile_of_block(b, tiles_x, tiles_y, bx, by, bz);
     StoreOut<Tin, Tout, UNSHARP> out{static_cast<Tout *>(a.out), static_cast<const Tin *>(a.in), taps.amount};
-    gauss_tile<Tin, R, D, StoreOut<Tin, Tout, UNSHARP>, PAR, fused_tx(R)>(a, taps, zlen, bx, by, bz, (int)(b & 3u),
-                                                                        out);
+    gauss_tile<Tin, R, D, StoreOut<Tin, Tout, UNSHARP>, PAR, fused_tx(R, UNSHARP)>(a, taps, zlen, bx, by, bz,
+                                                                                  (int)(b & 3u), out);
 }
 
 // Persistent batched Gaussian: workgroup b takes work items
@@ -652,46 +653,54 @@ __global__ __launch_bounds__(256) void gauss_pass_kernel(const Tin *src, int64_t
 template <typename Tin, typename Tout, int R, bool UNSHARP, int PAR = 0>
 void launch_fused_u(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
-    constexpr int NT = fused_tx(R) / 4 * kTY;
+    constexpr int TXF = fused_tx(R, UNSHARP);
+    constexpr int NT = TXF / 4 * kTY;
     static const int64_t cap = resident_blocks(gauss_fused_kernel<Tin, Tout, R, UNSHARP, PAR>, NT);
     Tile t;
-    const int code = tune_type_code<Tin>() * 8 + tune_type_code<Tout>() + (UNSHARP ? 64 : 0) + PAR * 128;
+    // the tile width is part of the key: z splits tuned for other tiles do
+    // not carry over
+    const int code = tune_type_code<Tin>() * 8 + tune_type_code<Tout>() + (UNSHARP ? 64 : 0) + PAR * 128 +
+                     TXF * 1024;
     const bool tuned = tune_lookup(TF_GAUSS, tune_key_volume(TF_GAUSS, R, code, a.out_e), t);
-    const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0, fused_tx(R));
+    const FusedGrid g = fused_grid(a, R, cap, tuned ? t.tz : 0, TXF);
     hipLaunchKernelGGL((gauss_fused_kernel<Tin, Tout, R, UNSHARP, PAR>), dim3((uint32_t)g.blocks), dim3(NT), 0, s,
                        a, fused_taps(taps), g.zlen, g.tiles_x, g.tiles_y);
 }
 
-// Odd taps (derivative filters: the mixed Hessian components) are built for
-// float32 -> float32 only; other pairs take the unfused path.
-template <typename Tin, typename Tout, int R>
-bool launch_fused(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
+// Three kernel families: plain smoothing (VAR 0), the unsharp epilogue
+// (VAR 1) and odd derivative taps (VAR 2: the mixed Hessian components,
+// built for float32 -> float32 only; other pairs take the unfused path).
+// Each family has its own radius dispatch, so that one dtype pair's families
+// can be compiled in separate units.
+template <typename Tin, typename Tout, int R, int VAR>
+bool launch_family(const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
-    if (taps.unsharp) {
+    if constexpr (VAR == 1) {
         launch_fused_u<Tin, Tout, R, true>(a, taps, s);
         return true;
-    }
-    if constexpr (std::is_same<Tin, float>::value && std::is_same<Tout, float>::value) {
-        switch (taps.odd) {
-        case 0: launch_fused_u<Tin, Tout, R, false, 0>(a, taps, s); return true;
-        case 3: launch_fused_u<Tin, Tout, R, false, 3>(a, taps, s); return true;
-        case 5: launch_fused_u<Tin, Tout, R, false, 5>(a, taps, s); return true;
-        case 6: launch_fused_u<Tin, Tout, R, false, 6>(a, taps, s); return true;
-        default: return false;
+    } else if constexpr (VAR == 2) {
+        if constexpr (std::is_same<Tin, float>::value && std::is_same<Tout, float>::value) {
+            switch (taps.odd) {
+            case 3: launch_fused_u<Tin, Tout, R, false, 3>(a, taps, s); return true;
+            case 5: launch_fused_u<Tin, Tout, R, false, 5>(a, taps, s); return true;
+            case 6: launch_fused_u<Tin, Tout, R, false, 6>(a, taps, s); return true;
+            default: return false;
+            }
         }
+        return false;
+    } else {
+        launch_fused_u<Tin, Tout, R, false, 0>(a, taps, s);
+        return true;
     }
-    if (taps.odd) return false;
-    launch_fused_u<Tin, Tout, R, false>(a, taps, s);
-    return true;
 }
 
-template <typename Tin, typename Tout>
-bool dispatch_fused(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
+template <typename Tin, typename Tout, int VAR>
+bool fused_family_run(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
 {
     switch (r) {
 #define HARPIA_CASE(RR) \
     case RR:            \
-        return launch_fused<Tin, Tout, RR>(a, taps, s);
+        return launch_family<Tin, Tout, RR, VAR>(a, taps, s);
         HARPIA_CASE(1)
         HARPIA_CASE(2)
         HARPIA_CASE(3)
@@ -706,8 +715,16 @@ bool dispatch_fused(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_
         HARPIA_CASE(12)
 #undef HARPIA_CASE
     default:
-        return -1;
+        return false;
     }
+}
+
+template <typename Tin, typename Tout>
+bool dispatch_fused(int r, const ChunkArgs &a, const GaussTaps &taps, hipStream_t s)
+{
+    if (taps.unsharp) return fused_family_run<Tin, Tout, 1>(r, a, taps, s);
+    if (taps.odd) return fused_family_run<Tin, Tout, 2>(r, a, taps, s);
+    return fused_family_run<Tin, Tout, 0>(r, a, taps, s);
 }
 
 template <typename Tin, typename Tout>

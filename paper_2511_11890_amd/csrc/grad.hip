@@ -114,8 +114,8 @@ __device__ __forceinline__ bool in_element(int se, int r, int dz, int dy, int dx
 
 // code[p] for every p of the output region (codes laid out like a.out, u16).
 template <typename T>
-__device__ __forceinline__ void argext_tile(const ChunkArgs &a, uint16_t *code, int op, int se, int rz, int ry,
-                                            int rx, int bx, int by, int bz, float *sv)
+__device__ __forceinline__ void argext_tile(const ChunkArgs &a, uint16_t *code, float *val, int op, int se, int rz,
+                                            int ry, int rx, int bx, int by, int bz, float *sv)
 {
     const TileGeom t = tile_geom(a, rz, ry, rx, bx, by, bz);
     const int n_lds = t.hz * t.hy * t.hx;
@@ -163,8 +163,9 @@ __device__ __forceinline__ void argext_tile(const ChunkArgs &a, uint16_t *code, 
                 }
             }
         }
-        code[(gz - a.out_o[0]) * a.out_sz + (gy - a.out_o[1]) * a.out_sy + (gx - a.out_o[2])] =
-            (uint16_t)best_code;
+        const int64_t o = (gz - a.out_o[0]) * a.out_sz + (gy - a.out_o[1]) * a.out_sy + (gx - a.out_o[2]);
+        code[o] = (uint16_t)best_code;
+        if (val) val[o] = best;  // the erosion / dilation itself
     }
 }
 
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(kGT) void argext_kernel(ChunkArgs a, uint16_t *code
     extern __shared__ float sv[];
     int bx, by, bz;
     block_tile(tiles_x, tiles_y, bx, by, bz);
-    argext_tile<T>(a, code, op, se, rz, ry, rx, bx, by, bz, sv);
+    argext_tile<T>(a, code, nullptr, op, se, rz, ry, rx, bx, by, bz, sv);
 }
 
 // Batched: in = volume, aux = code volume (written).
@@ -188,8 +189,8 @@ __global__ __launch_bounds__(kGT) void argext_batched_kernel(BatchDesc d, int op
         int c, bx, by, bz;
         batch_item(d, w, c, bx, by, bz);
         const ChunkArgs a = crop_args(d.c[c]);
-        argext_tile<T>(a, static_cast<uint16_t *>(const_cast<void *>(d.c[c].aux)), op, se, rz, ry, rx, bx, by, bz,
-                       sv);
+        argext_tile<T>(a, static_cast<uint16_t *>(const_cast<void *>(d.c[c].aux)), static_cast<float *>(d.c[c].out),
+                       op, se, rz, ry, rx, bx, by, bz, sv);
         lds_barrier();
     }
 }
@@ -319,6 +320,7 @@ __global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, in
         const BatchCrop &k = d.c[c];
         const T *in = static_cast<const T *>(k.in);
         uint16_t *code = static_cast<uint16_t *>(const_cast<void *>(k.aux));
+        float *vout = static_cast<float *>(k.out);  // the extremum itself, if wanted
         const int nz = k.n[0], ny = k.n[1], nx = k.n[2];
         const int64_t plane = (int64_t)ny * nx;
         const int x0 = bx * TX, y0 = by * TY;
@@ -423,6 +425,7 @@ __global__ __launch_bounds__(kSepThreads) void argext_box_kernel(BatchDesc d, in
                         }
                     }
                     code[(int64_t)zo * plane + (int64_t)gy * nx + gx] = (uint16_t)(pc[so * P + e] | (bi + rz) << 10);
+                    if (vout) vout[(int64_t)zo * plane + (int64_t)gy * nx + gx] = erode ? -best : best;
                 }
             }
             slot = slot + 1 == W ? 0 : slot + 1;

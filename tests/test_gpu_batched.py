@@ -159,10 +159,10 @@ def test_c5_batch_sizes_one_launch_per_kernel(dev):
         b.forward()
         b.backward(cs)
     launches = _kernel_nodes(g)
-    # forward: Gaussian, dilation; backward: Gaussian (recompute),
-    # extremum codes, gather, Gaussian of the routed gradient, sigma terms,
-    # FP64 reduction
-    assert launches == 8, launches
+    # forward: Gaussian, dilation with its extremum codes; backward: gather
+    # through the codes, Gaussian of the routed gradient, sigma terms, FP64
+    # reduction
+    assert launches == 6, launches
     for t in b.ds + b.gxs:
         t.zero_()
     g.replay()
@@ -183,6 +183,39 @@ def test_c5_batch_sizes_one_launch_per_kernel(dev):
             assert np.all(err <= 1e-5 * scale + 1e-7), (i, float(np.max(err - 1e-5 * scale)))
             assert abs(t - gso) <= 1e-4 * abs(gso) + 1e-6, (i, t, gso)
     assert abs(b.gsigma.item() - tot) <= 1e-5 * mag
+
+
+@pytest.mark.parametrize("op,se,r", [("dilate", "box", 2), ("erode", "ball", 3), ("erode", "box", 1),
+                                     ("dilate", "ball", 2)])
+def test_forward_codes_reused_by_backward(dev, op, se, r):
+    # harpia_morph3d_forward_batched: the erosion / dilation equals the
+    # per-crop call, and the backward through its kept codes equals the
+    # backward that recomputes them (and the per-crop subgradient)
+    xs = _crops(dev, n=20, seed=58)
+    gds = [phantoms.gaussian_noise(x.shape, seed=300 + i).to(dev) for i, x in enumerate(xs)]
+    lib = h._lib.load()
+    code = {"erode": h._lib.HARPIA_ERODE, "dilate": h._lib.HARPIA_DILATE}[op]
+    sc = {"box": 0, "ball": 1}[se]
+    outs = [torch.empty_like(x) for x in xs]
+    c_fwd = h._lib.crops([(x, o, None) for x, o in zip(xs, outs)])
+    ws = torch.empty(int(lib.harpia_batch_workspace_bytes(c_fwd, len(xs))), dtype=torch.uint8, device=dev)
+    st = lambda f=0: h._lib.make_exec(stream=torch.cuda.current_stream().cuda_stream, flags=f)  # noqa: E731
+    r3 = h._lib.i32_3((r, r, r))
+    h._lib.check(lib.harpia_morph3d_forward_batched(c_fwd, len(xs), code, sc, r3, ws.data_ptr(), ws.numel(), st()))
+    g_reuse = [torch.empty_like(x) for x in xs]
+    h._lib.check(lib.harpia_morph3d_backward_batched(
+        h._lib.crops([(None, gi, gd) for gi, gd in zip(g_reuse, gds)]), len(xs), code, sc, r3, ws.data_ptr(),
+        ws.numel(), st(h._lib.HARPIA_F_REUSE_CODES)))
+    g_new = [torch.empty_like(x) for x in xs]
+    h._lib.check(lib.harpia_morph3d_backward_batched(
+        h._lib.crops([(x, gi, gd) for x, gi, gd in zip(xs, g_new, gds)]), len(xs), code, sc, r3, ws.data_ptr(),
+        ws.numel(), st()))
+    torch.cuda.synchronize()
+    f = h.erode if op == "erode" else h.dilate
+    for x, o, gd, a, b in zip(xs, outs, gds, g_reuse, g_new):
+        assert torch.equal(o, f(x, se, r))
+        assert torch.equal(a, b)
+        assert torch.equal(a, h.morph_backward(x, gd, op, se, r))
 
 
 def test_graph_replay_equals_eager(dev):
