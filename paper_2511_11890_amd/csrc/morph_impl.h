@@ -25,8 +25,9 @@
 //      of the level planes over its rows;
 //   4. z: a register ring of 2r+1 running extrema per column; slice s feeds
 //      class |o - s| into output o, and output s - r is complete.
-// Binary data is packed 4 voxels per 32-bit word (one byte each, 0 or 1):
-// extrema become AND / OR on words and x shifts are byte funnel shifts.
+// Binary data runs on bit rows (bits_kernel): a lane holds a row of 64
+// voxels as a 64-bit mask, extrema become OR on masks, x shifts are mask
+// shifts and y neighbours come from other lanes by cross-lane shuffles.
 #pragma once
 
 #include <cstdint>
@@ -342,30 +343,28 @@ __global__ __launch_bounds__(kGNT) void gray_batched_kernel(BatchDesc d, float s
 
 // ---------------------------------------------------------------- binary
 
-constexpr int kBTX = 256;             // voxels per tile row (64 words)
-constexpr int kBTY = 16;
-constexpr int kBW = kBTX / 4;         // words per tile row
-constexpr int kBPW = kBW + 2;         // patch words per row (1 halo word a side)
-
-__device__ __forceinline__ uint32_t funnel_bytes(uint32_t hi, uint32_t lo, int k)
-{
-    // bytes k..k+3 of the 8-byte little-endian value hi:lo (0 <= k <= 4)
-    return (uint32_t)((((uint64_t)hi << 32) | lo) >> (8 * k));
-}
-
-// Store 16 output bytes (4 packed words), or the first `nvalid` of them.
-__device__ __forceinline__ void emit16(uint8_t *p, uint4 w, int nvalid)
-{
-    if (nvalid == 16 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
-        *reinterpret_cast<uint4 *>(p) = w;
-        return;
-    }
-    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-        if (q < nvalid) p[q] = (uint8_t)((ws[q >> 2] >> (8 * (q & 3))) & 0xffu);
-}
-
+// Binary erosion / dilation on bit rows.
+//
+// A wave owns a strip of kBX = 64 output columns and streams along z; lane l
+// holds input row y_w - R + l of the strip (64 rows: the wave's 64 - 2R
+// output rows plus R halo rows on each side), four waves stack in y.  A row
+// of a slice is one 64-bit mask (bit i: voxel x0 + i is set) plus the 4
+// voxels on each side (enough for R <= 4).  Dilation:
+//   x runs      D_h = OR over |k| <= h of the row shifted by k (mask shifts
+//               with the halo bits carried in);
+//   discs       for each z-class c = |dz|, the OR over rows |dy| <= rho_c of
+//               D_{hw(c, dy)} of row y + dy, taken from lane l + dy by a
+//               cross-lane shuffle;
+//   z           a ring of 2R + 1 running ORs per lane; slice s feeds the
+//               disc of class |o - s| into output o, and output s - R is then
+//               complete and written as bytes.
+// Erosion is the complement of the dilation of the complement.  Voxels
+// outside the volume are 0 in the mask that is dilated (for these elements
+// ignoring them is the reflect boundary), and so are voxels farther than R
+// from the output region (no stored output reads them).  No LDS, no
+// barriers: the waves are independent.
+// 1 if v counts as set: v > thr (use_thr; thr is the largest value of the
+// input's type not above the threshold, so the comparison is exact) or v != 0.
 template <typename Tin>
 __device__ __forceinline__ uint32_t binarise(Tin v, float thr, bool use_thr)
 {
@@ -373,195 +372,260 @@ __device__ __forceinline__ uint32_t binarise(Tin v, float thr, bool use_thr)
     return use_thr ? (f > thr ? 1u : 0u) : (f != 0.f ? 1u : 0u);
 }
 
-// Binary erosion / dilation: u8 {0, 1} output.  `flip` = 1 computes an
-// erosion (complement in and out), 0 a dilation; BOTH writes the erosion to
-// out and the dilation to out2.
-template <typename Tin, int SE, int R, bool BOTH>
-__global__ __launch_bounds__(kNT) void binary_kernel(ChunkArgs a, Out2 o2, uint32_t flip, float thr, int use_thr,
-                                                     int tiles_x, int tiles_y, int zlen)
+constexpr int kBX = 64;               // output columns per wave
+constexpr int kBG = kBX / 4 + 2;      // 4-voxel groups per row: halo, 16 core, halo
+constexpr int kBNT = 256;             // threads per workgroup (4 waves)
+
+template <int R>
+constexpr int bits_rows() { return 64 - 2 * R; }  // output rows per wave
+
+// Raw storage of one 4-voxel group: 4 elements of Tin.
+template <typename Tin>
+struct Group4 {
+    static constexpr int W = (int)sizeof(Tin);  // 32-bit words per group
+    uint32_t w[W];
+};
+
+template <typename Tin>
+__device__ __forceinline__ Tin group_elem(const Group4<Tin> &g, int j)
 {
-    static_assert(R >= 1 && R <= 4, "one halo word per side");
+    Tin v;
+    __builtin_memcpy(&v, reinterpret_cast<const char *>(g.w) + j * sizeof(Tin), sizeof(Tin));
+    return v;
+}
+
+template <typename Tin>
+__device__ __forceinline__ void group_load4(Group4<Tin> &g, const Tin *p)
+{
+    if constexpr (sizeof(Tin) == 1) {
+        g.w[0] = *reinterpret_cast<const uint32_t *>(p);
+    } else if constexpr (sizeof(Tin) == 2) {
+        const uint2 t = *reinterpret_cast<const uint2 *>(p);
+        g.w[0] = t.x;
+        g.w[1] = t.y;
+    } else {
+        const uint4 t = *reinterpret_cast<const uint4 *>(p);
+        g.w[0] = t.x;
+        g.w[1] = t.y;
+        g.w[2] = t.z;
+        g.w[3] = t.w;
+    }
+}
+
+template <typename Tin>
+__device__ __forceinline__ void group_set(Group4<Tin> &g, int j, Tin v)
+{
+    __builtin_memcpy(reinterpret_cast<char *>(g.w) + j * sizeof(Tin), &v, sizeof(Tin));
+}
+
+// 16 output bytes (voxel order) from 16 bits.
+__device__ __forceinline__ uint4 bits_to_bytes16(uint32_t b)
+{
+    // nibble n (bits b3 b2 b1 b0) -> bytes b0 b1 b2 b3: the four shifted
+    // copies of n * 0x204081 do not overlap, so bit 8j holds b_j
+    uint32_t q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = (((b >> (4 * j)) & 0xfu) * 0x204081u) & 0x01010101u;
+    return make_uint4(q[0], q[1], q[2], q[3]);
+}
+
+template <typename Tin, int SE, int R, bool BOTH>
+__global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32_t flip, float thr, int use_thr,
+                                                    int vec_in, int vec_out, int tiles_x, int tiles_y, int zlen)
+{
+    static_assert(R >= 1 && R <= 4, "4 halo voxels per side");
     using S = Shape<SE, R>;
     constexpr int P = 2 * R + 1;
-    constexpr int PH = kBTY + 2 * R;
-    constexpr int NWI = kBPW * PH;                 // patch words
-    constexpr int NLW = (NWI + kNT - 1) / kNT;     // words loaded per thread
-    constexpr int NA = kBW * PH;                   // stage A items
-    constexpr int NM = BOTH ? 2 : 1;               // 0: OR (dilation), 1: AND
-    const uint32_t fmask = flip ? 0x01010101u : 0u;
+    constexpr int NM = BOTH ? 2 : 1;  // pipeline m = 0: dilation of b (BOTH) or of b ^ flip; m = 1: of ~b
+    constexpr int YR = bits_rows<R>();
 
-    __shared__ uint32_t sP[PH * kBPW];
-    __shared__ __attribute__((aligned(16))) uint32_t sH[NM][S::NL][PH * kBW];
-
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = (int)(b % (uint32_t)tiles_x);
     const int by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
     const int bz = (int)(b / (uint32_t)(tiles_x * tiles_y));
 
-    const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
-    const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1];
-    const int64_t x0 = xbeg + (int64_t)bx * kBTX;
-    const int64_t y0 = ybeg + (int64_t)by * kBTY;
-    const int64_t zo0 = a.out_o[0] + (int64_t)bz * zlen;
-    const int64_t zo1 = min(zo0 + (int64_t)zlen, a.out_o[0] + a.out_e[0]);
-    if (zo0 >= zo1) return;
+    const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1], zbeg = a.out_o[0];
+    const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1], zend = zbeg + a.out_e[0];
+    const int64_t x0 = xbeg + (int64_t)bx * kBX;
+    const int64_t yw = ybeg + ((int64_t)by * 4 + wave) * YR;  // first output row of this wave
+    const int64_t zo0 = zbeg + (int64_t)bz * zlen;
+    const int64_t zo1 = min(zo0 + (int64_t)zlen, zend);
+    if (zo0 >= zo1 || yw >= yend) return;
 
-    // Each loaded word holds patch columns 4w-4 .. 4w-1 relative to x0.  Its
-    // source offset is kept when the 4 voxels are consecutive in memory;
-    // words that cross a face or the clamp (-1) are resolved per voxel.
-    int32_t off[NLW];
-#pragma unroll
-    for (int i = 0; i < NLW; ++i) {
-        const int e = tid + i * kNT;
-        off[i] = 0;
-        if (e < NWI) {
-            const int row = e / kBPW, w = e - (e / kBPW) * kBPW;
-            int64_t gy = y0 - R + row;
-            gy = gy < ybeg - R ? ybeg - R : (gy > yend - 1 + R ? yend - 1 + R : gy);
-            const int64_t ly = reflect_index(gy, a.n[1]) - a.in_o[1];
-            const int64_t gx = x0 - 4 + 4 * w;
-            if (gx >= 0 && gx + 3 < a.n[2] && gx >= xbeg - R && gx + 3 <= xend - 1 + R)
-                off[i] = (int32_t)(ly * a.in_sy + (gx - a.in_o[2]));
-            else
-                off[i] = -1 - (int32_t)ly;  // slow path marker, keeps the row
-        }
-    }
+    // window of voxels that may be read: the volume, within R of the output
+    // region
+    const int64_t xlo = max((int64_t)0, xbeg - R), xhi = min(a.n[2], xend + R);
+    const int64_t ylo = max((int64_t)0, ybeg - R), yhi = min(a.n[1], yend + R);
+    const int64_t zlo = max((int64_t)0, zbeg - R), zhi = min(a.n[0], zend + R);
+
+    const int64_t y = yw - R + lane;
+    const bool row_in = y >= ylo && y < yhi;
+    const Tin *in = static_cast<const Tin *>(a.in);
+    const Tin *row_base = in + (row_in ? (y - a.in_o[1]) * a.in_sy : 0) - a.in_o[2];
+
+    // in-window mask of the strip (the same for every lane): bit k of the
+    // group-g nibble is voxel x0 - 4 + 4 g + k
+    auto in_x = [&](int64_t x) __attribute__((always_inline)) { return x >= xlo && x < xhi; };
 
     const int64_t s0 = zo0 - R;
     const int nsteps = (int)(zo1 - zo0) + 2 * R;
-    const Tin *in = static_cast<const Tin *>(a.in);
-    // The next slice, packed on load (unconditional fetch, clamped at the end).
-    uint32_t pf[NLW];
+
+    Group4<Tin> raw[kBG];
     auto fetch = [&](int j) __attribute__((always_inline)) {
-        j = j < nsteps ? j : nsteps - 1;
-        const Tin *base = in + (reflect_index(s0 + j, a.n[0]) - a.in_o[0]) * a.in_sz;
+        const int64_t z = s0 + (j < nsteps ? j : nsteps - 1);
+        if (!row_in || z < zlo || z >= zhi) return;
+        const Tin *p = row_base + (z - a.in_o[0]) * a.in_sz;
 #pragma unroll
-        for (int i = 0; i < NLW; ++i) {
-            if (i < NLW - 1 || tid + i * kNT < NWI) {
-                uint32_t wv = 0;
-                if (off[i] >= 0) {
-                    const Tin *p = base + off[i];
+        for (int g = 0; g < kBG; ++g) {
+            const int64_t xg = x0 - 4 + 4 * g;
+            if (vec_in && in_x(xg) && in_x(xg + 3)) {
+                group_load4<Tin>(raw[g], p + xg);
+            } else {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) wv |= binarise(p[j], thr, use_thr) << (8 * j);
-                } else {
-                    const int e = tid + i * kNT;
-                    const int w = e % kBPW;
-                    const int64_t ly = -1 - (int64_t)off[i];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        int64_t gx = x0 - 4 + 4 * w + j;
-                        gx = gx < xbeg - R ? xbeg - R : (gx > xend - 1 + R ? xend - 1 + R : gx);
-                        const int64_t lx = reflect_index(gx, a.n[2]) - a.in_o[2];
-                        wv |= binarise(base[ly * a.in_sy + lx], thr, use_thr) << (8 * j);
-                    }
-                }
-                pf[i] = wv;
+                for (int k = 0; k < 4; ++k)
+                    if (in_x(xg + k)) group_set<Tin>(raw[g], k, p[xg + k]);
             }
         }
     };
+    // bits of slice j from raw: row mask, left halo (bits 0..3 = x0-4..x0-1),
+    // right halo (bits 0..3 = x0+64..x0+67); 0 outside the window.  Returns
+    // whether the row lies in the window (else its complement is 0 too).
+    auto pack = [&](int j, uint64_t &m, uint32_t &hl, uint32_t &hr) __attribute__((always_inline)) -> bool {
+        m = 0;
+        hl = hr = 0;
+        const int64_t z = s0 + j;
+        if (!row_in || z < zlo || z >= zhi) return false;
+#pragma unroll
+        for (int g = 0; g < kBG; ++g) {
+            const int64_t xg = x0 - 4 + 4 * g;
+            uint32_t nib = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (in_x(xg + k)) nib |= binarise(group_elem<Tin>(raw[g], k), thr, use_thr) << k;
+            if (g == 0)
+                hl = nib;
+            else if (g == kBG - 1)
+                hr = nib;
+            else
+                m |= (uint64_t)nib << (4 * (g - 1));
+        }
+        return true;
+    };
+    // window masks of the strip (for complements)
+    uint64_t wm = 0;
+    uint32_t wl = 0, wr = 0;
+#pragma unroll
+    for (int g = 0; g < kBG; ++g) {
+        const int64_t xg = x0 - 4 + 4 * g;
+        uint32_t nib = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (in_x(xg + k)) nib |= 1u << k;
+        if (g == 0)
+            wl = nib;
+        else if (g == kBG - 1)
+            wr = nib;
+        else
+            wm |= (uint64_t)nib << (4 * (g - 1));
+    }
 
-    const int qrow = tid / (kBW / 4);
-    const int qw = (tid % (kBW / 4)) * 4;  // first word of this thread's quad
-    const int64_t gy_out = y0 + qrow;
-    const int64_t gx_out = x0 + 4 * qw;
-    const int nvalid = (gy_out < yend) ? (int)min((int64_t)16, xend - gx_out) : 0;
-    uint8_t *outp = static_cast<uint8_t *>(a.out) + (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
-    uint8_t *outp2 = BOTH ? static_cast<uint8_t *>(o2.ptr) + (gy_out - ybeg) * o2.sy + (gx_out - xbeg) : nullptr;
+    const bool out_row = lane >= R && lane < 64 - R && y < yend;
+    const int64_t nx_out = xend - x0;  // valid output columns of the strip (may exceed 64)
+    uint8_t *outp = static_cast<uint8_t *>(a.out) + (y - ybeg) * a.out_sy + (x0 - xbeg);
+    uint8_t *outp2 = BOTH ? static_cast<uint8_t *>(o2.ptr) + (y - ybeg) * o2.sy + (x0 - xbeg) : nullptr;
+    auto emit = [&](uint8_t *p, uint64_t v) __attribute__((always_inline)) {
+        if (vec_out && nx_out >= kBX) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) reinterpret_cast<uint4 *>(p)[q] = bits_to_bytes16((uint32_t)(v >> (16 * q)));
+        } else {
+#pragma unroll
+            for (int i = 0; i < kBX; ++i)
+                if (i < nx_out) p[i] = (uint8_t)((v >> i) & 1u);
+        }
+    };
 
-    uint32_t acc[NM][P][4];
+    uint64_t acc[NM][P];
 #pragma unroll
     for (int m = 0; m < NM; ++m)
 #pragma unroll
-        for (int j = 0; j < P; ++j)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[m][j][c] = 0u;
+        for (int j = 0; j < P; ++j) acc[m][j] = 0;
 
     fetch(0);
-
-    for (int base = 0; base <= nsteps; base += P) {
+    for (int base = 0; base < nsteps; base += P) {
         static_for<P>([&](auto U) {
             constexpr int u = decltype(U)::value;
             const int i = base + u;
-            if (i > nsteps) return;
-            if (i < nsteps) {
-#pragma unroll
-                for (int k = 0; k < NLW; ++k)
-                    if (k < NLW - 1 || tid + k * kNT < NWI) sP[tid + k * kNT] = BOTH ? pf[k] : (pf[k] ^ fmask);
-                fetch(i + 1);
-            }
-            if (i >= 1 && i - 1 >= 2 * R && nvalid > 0) {
-                constexpr int sl = (u - 1 - R + 2 * P) % P;
-                const int64_t zl = s0 + (i - 1) - R - a.out_o[0];
-                if constexpr (BOTH) {
-                    emit16(outp + zl * a.out_sz, make_uint4(acc[1][sl][0], acc[1][sl][1], acc[1][sl][2], acc[1][sl][3]),
-                           nvalid);
-                    emit16(outp2 + zl * o2.sz, make_uint4(acc[0][sl][0], acc[0][sl][1], acc[0][sl][2], acc[0][sl][3]),
-                           nvalid);
-                } else {
-                    emit16(outp + zl * a.out_sz,
-                           make_uint4(acc[0][sl][0] ^ fmask, acc[0][sl][1] ^ fmask, acc[0][sl][2] ^ fmask,
-                                      acc[0][sl][3] ^ fmask),
-                           nvalid);
-                }
-            }
             if (i >= nsteps) return;
-            lds_barrier();
-
-            // stage A: word-level x runs (OR for m = 0, AND for m = 1)
-#pragma unroll
-            for (int itk = 0; itk < (NA + kNT - 1) / kNT; ++itk) {
-                const int it = tid + itk * kNT;
-                if (itk == (NA + kNT - 1) / kNT - 1 && it >= NA) continue;
-                const int row = it / kBW, w = it - (it / kBW) * kBW;
-                const uint32_t wl = sP[row * kBPW + w];
-                const uint32_t wc = sP[row * kBPW + w + 1];
-                const uint32_t wr = sP[row * kBPW + w + 2];
-#pragma unroll
-                for (int m = 0; m < NM; ++m) {
-                    uint32_t run = wc;
-                    static_for<R + 1>([&](auto H) {
-                        constexpr int h = decltype(H)::value;
-                        if constexpr (h > 0) {
-                            const uint32_t sr = funnel_bytes(wr, wc, h);      // voxel x + h
-                            const uint32_t sl2 = funnel_bytes(wc, wl, 4 - h); // voxel x - h
-                            run = (m == 0) ? (run | sr | sl2) : (run & sr & sl2);
-                        }
-                        if constexpr (SE != HARPIA_SE_BOX || h == R) sH[m][S::lvl(h)][row * kBW + w] = run;
-                    });
-                }
+            uint64_t row[NM];
+            uint32_t hl[NM], hr[NM];
+            const bool live = pack(i, row[0], hl[0], hr[0]);
+            fetch(i + 1);
+            // complement within the window (voxels outside stay 0)
+            const uint64_t cm = live ? wm : 0;
+            const uint32_t cl = live ? wl : 0, cr = live ? wr : 0;
+            if constexpr (BOTH) {
+                row[1] = ~row[0] & cm;
+                hl[1] = ~hl[0] & cl;
+                hr[1] = ~hr[0] & cr;
+            } else if (flip) {
+                row[0] = ~row[0] & cm;
+                hl[0] = ~hl[0] & cl;
+                hr[0] = ~hr[0] & cr;
             }
-            lds_barrier();
-
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
-                static_for<S::NC>([&](auto C) {
-                    constexpr int c = decltype(C)::value;
-                    constexpr int rh = S::rho(c);
-                    uint32_t dv[4];
-                    static_for<2 * rh + 1>([&](auto DY) {
-                        constexpr int dy = decltype(DY)::value - rh;
-                        constexpr int l = S::lvl(S::hw(c, dy));
-                        const uint4 t4 = *reinterpret_cast<const uint4 *>(&sH[m][l][(qrow + R + dy) * kBW + qw]);
-                        const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
+                // x runs of every half-width up to R
+                uint64_t dlev[R + 1];
+                dlev[0] = row[m];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            if constexpr (dy == -rh) dv[q] = tv[q];
-                            else dv[q] = (m == 0) ? (dv[q] | tv[q]) : (dv[q] & tv[q]);
-                        }
-                    });
-                    static_for<P>([&](auto DD) {
-                        constexpr int d = decltype(DD)::value - R;
-                        if constexpr (S::cls(d) == c) {
-                            constexpr int sl = (u + d + 2 * P) % P;
+                for (int h = 1; h <= R; ++h) {
+                    const uint64_t up = (row[m] >> h) | ((uint64_t)hr[m] << (64 - h));    // voxel x + h
+                    const uint64_t dn = (row[m] << h) | (uint64_t)(hl[m] >> (4 - h));     // voxel x - h
+                    dlev[h] = dlev[h - 1] | up | dn;
+                }
+                // discs of the z-classes from the rows of lanes l + dy
+                uint64_t disc[S::NC];
 #pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                acc[m][sl][q] = (d == R) ? dv[q]
-                                                         : ((m == 0) ? (acc[m][sl][q] | dv[q])
-                                                                     : (acc[m][sl][q] & dv[q]));
+                for (int c = 0; c < S::NC; ++c) disc[c] = 0;
+                static_for<P>([&](auto DY) {
+                    constexpr int dy = decltype(DY)::value - R;
+                    static_for<R + 1>([&](auto H) {
+                        constexpr int h = decltype(H)::value;
+                        constexpr bool used = [] {
+                            for (int c = 0; c < S::NC; ++c)
+                                if (S::takes(c, dy, h)) return true;
+                            return false;
+                        }();
+                        if constexpr (used) {
+                            const uint64_t v = dy == 0 ? dlev[h] : (uint64_t)__shfl(dlev[h], lane + dy, 64);
+                            static_for<S::NC>([&](auto C) {
+                                constexpr int c = decltype(C)::value;
+                                if constexpr (S::takes(c, dy, h)) disc[c] |= v;
+                            });
                         }
                     });
                 });
+                // z ring: slice i feeds output s0 + i + d, slot (i + d) mod P
+                static_for<P>([&](auto DD) {
+                    constexpr int d = decltype(DD)::value - R;
+                    constexpr int sl = (u + d + 2 * P) % P;
+                    acc[m][sl] = (d == R) ? disc[S::cls(d)] : (acc[m][sl] | disc[S::cls(d)]);
+                });
+            }
+            // output s0 + i - R is complete
+            if (i >= 2 * R && out_row) {
+                constexpr int sl = (u - R + 2 * P) % P;
+                const int64_t o = s0 + i - R;
+                if (o < zo1) {
+                    const int64_t zl = o - zbeg;
+                    if constexpr (BOTH) {
+                        emit(outp + zl * a.out_sz, ~acc[1][sl]);  // erosion
+                        emit(outp2 + zl * o2.sz, acc[0][sl]);     // dilation
+                    } else {
+                        emit(outp + zl * a.out_sz, flip ? ~acc[0][sl] : acc[0][sl]);
+                    }
+                }
             }
         });
     }
@@ -623,14 +687,22 @@ template <typename T, int SE, int R, bool BOTH>
 void launch_fast(const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float thr_f, hipStream_t s)
 {
     if (m.binary) {
-        static const int64_t cap = resident_blocks(binary_kernel<T, SE, R, BOTH>, kNT);
+        static const int64_t cap = resident_blocks(bits_kernel<T, SE, R, BOTH>, kBNT);
         Tile t;
-        const bool tuned = tune_lookup(
-            TF_BINARY, tune_key_volume(TF_BINARY, R * 4 + SE * 2 + (BOTH ? 1 : 0), tune_type_code<T>(), a.out_e), t);
-        const Grid g = make_grid(a, kBTX, kBTY, R, cap, tuned ? t.tz : 0);
-        hipLaunchKernelGGL((binary_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kNT), 0, s, a, o2,
-                           (uint32_t)(m.op == 0 ? 1u : 0u), thr_f, (int)m.has_threshold, g.tiles_x, g.tiles_y,
-                           g.zlen);
+        // the kernel generation is part of the key: z splits tuned for other
+        // kernels do not carry over
+        const bool tuned = tune_lookup(TF_BINARY, tune_key_volume(TF_BINARY, R * 4 + SE * 2 + (BOTH ? 1 : 0),
+                                                                  tune_type_code<T>() + 16, a.out_e),
+                                       t);
+        const Grid g = make_grid(a, kBX, 4 * bits_rows<R>(), R, cap, tuned ? t.tz : 0);
+        // 4-voxel input groups and 16-byte output rows are aligned?
+        const int vec_in = ((uintptr_t)a.in % (4 * sizeof(T)) == 0) && a.in_sy % 4 == 0 && a.in_sz % 4 == 0 &&
+                           (a.out_o[2] - a.in_o[2]) % 4 == 0;
+        int vec_out = ((uintptr_t)a.out % 16 == 0) && a.out_sy % 16 == 0 && a.out_sz % 16 == 0;
+        if (BOTH) vec_out = vec_out && ((uintptr_t)o2.ptr % 16 == 0) && o2.sy % 16 == 0 && o2.sz % 16 == 0;
+        hipLaunchKernelGGL((bits_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kBNT), 0, s, a, o2,
+                           (uint32_t)(m.op == 0 ? 1u : 0u), thr_f, (int)m.has_threshold, vec_in, vec_out,
+                           g.tiles_x, g.tiles_y, g.zlen);
     } else {
         static const int64_t cap = resident_blocks(gray_kernel<T, SE, R, BOTH>, gray_nt(R));
         Tile t;
