@@ -57,6 +57,12 @@ KERNEL_SOURCES = {
               "paper_2511_11890_amd/csrc/morph_f32.hip"],
 }
 
+# kernel-name fragments of the 2048^3 FP32 ops of the headline step
+HEADLINE_KERNELS = {
+    "f32_sigma1": ("gauss", "gauss_fused_kernel<float, float, 3,"),
+    "f32_sigma4": ("gauss", "gauss_fused_kernel<float, float, 12,"),
+}
+
 # kernel-name fragments of the resident workload's ops (f32, fused kernels)
 RESIDENT_KERNELS = {
     "gauss_s1": ("gauss", "gauss_fused_kernel<float, float, 3,"),
@@ -137,17 +143,18 @@ def stats_summary(root: str, command: str, title: str) -> str:
     return "\n".join(lines) + "\n"
 
 
-def traffic_summary(fetch_root: str, write_root: str, size: int, commands) -> dict:
-    """HBM bytes per launch of the resident ops from two `rocprofv3 --pmc`
-    runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
-    `bench.py --copy-ref`.  Each counter is scaled by what it reads for the
-    plain device copy of the volume in the same run (the largest copy
-    dispatch: 4 * size^3 bytes read and written)."""
+def traffic_summary(fetch_root: str, write_root: str, size: int, commands, kernels=None) -> dict:
+    """HBM bytes per launch of the ops in `kernels` (default: the resident
+    ops) from two `rocprofv3 --pmc` runs (FETCH_SIZE, then WRITE_SIZE; KiB
+    per dispatch) of a bench command with --copy-ref.  Each counter is scaled
+    by what it reads for the plain device copy of the volume in the same run
+    (the largest copy dispatch: 4 * size^3 bytes read and written)."""
+    kernels = RESIDENT_KERNELS if kernels is None else kernels
     vox = size ** 3
     copy_kib = 4.0 * vox / 1024.0
     out = {"size": size, "commands": list(commands), "source_sha": {k: sources_sha(k) for k in KERNEL_SOURCES},
            "copy_ref": {}, "ops": {}}
-    per_op = {op: {} for op in RESIDENT_KERNELS}
+    per_op = {op: {} for op in kernels}
     for counter, root in (("FETCH_SIZE", fetch_root), ("WRITE_SIZE", write_root)):
         rows = [r for r in _csv_rows(root, "counter_collection.csv") if r["Counter_Name"] == counter]
         copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
@@ -156,7 +163,7 @@ def traffic_summary(fetch_root: str, write_root: str, size: int, commands) -> di
         ref = max(copies)
         scale = copy_kib / ref
         out["copy_ref"][counter] = {"kib": ref, "expected_kib": copy_kib, "scale": round(scale, 4)}
-        for op, (_, pat) in RESIDENT_KERNELS.items():
+        for op, (_, pat) in kernels.items():
             vals = [float(r["Counter_Value"]) for r in rows if pat in r["Kernel_Name"]]
             if vals:
                 per_op[op][counter] = (sum(vals) / len(vals), len(vals), scale)
@@ -452,11 +459,15 @@ def run_headline(args):
     dev = torch.device("cuda:0")
     n = args.size
     tiles = tiles_load(args.tiles)
+    tuned = {}
     print("headline: phantom %d^3" % n, file=sys.stderr, flush=True)
     v = torch.clamp(phantoms.porous((n, n, n), seed=0, device=dev), 0.0, 1.0)
     vox = v.numel()
     out = torch.empty_like(v)
     radius = {1.0: 3, 4.0: 12}
+    if args.tune:
+        for s in radius:
+            tuned["f32_sigma%g" % s] = h.autotune_gaussian(v, s, out=out)
     step_ops = [("f32_sigma1", lambda: h.gaussian(v, 1.0, out=out)), ("f32_sigma4", lambda: h.gaussian(v, 4.0, out=out))]
     ms_step, ms = time_ops(step_ops, args.steps, args.warmup)
 
@@ -496,6 +507,9 @@ def run_headline(args):
         print("headline: %s" % tag, file=sys.stderr, flush=True)
         x = v.to(dt)
         y = torch.empty_like(x)
+        if args.tune:
+            for s in radius:
+                tuned["%s_sigma%g" % (tag, s)] = h.autotune_gaussian(x, s, out=y)
         ops16 = [("%s_sigma%g" % (tag, s), (lambda s=s: h.gaussian(x, s, out=y))) for s in radius]
         _, ms16 = time_ops(ops16, args.steps, args.warmup)
         deq = [reflect_window(x, o, b, rmax) for o in blocks]
@@ -537,7 +551,11 @@ def run_headline(args):
     del v
     torch.cuda.empty_cache()
     print("headline: resident 1024^3 ops", file=sys.stderr, flush=True)
-    vr, res_ops, res_ms_step, copy_gbs, _ = resident_measure(1024, args.steps, args.warmup, tiles_path=args.tiles)
+    vr, res_ops, res_ms_step, copy_gbs, res_tiles = resident_measure(1024, args.steps, args.warmup, tune=args.tune,
+                                                                     tiles_path=args.tiles)
+    if args.tune:
+        tiles = res_tiles
+        tiles["report"] = dict(tuned, resident_1024=res_tiles.get("report"))
     del vr
     torch.cuda.empty_cache()
     per_op["resident_1024"] = dict(res_ops, step_ms=round(res_ms_step, 3),
@@ -577,6 +595,13 @@ def run_precision(args):
     dev = torch.device("cuda:0")
     n = args.size
     v = torch.clamp(phantoms.porous((n, n, n), seed=0, device=dev), 0, 1)
+    tiles_load(args.tiles)
+    if args.copy_ref:
+        # a plain device copy of the volume (reference for HBM counters)
+        w = torch.empty_like(v)
+        w.copy_(v)
+        torch.cuda.synchronize()
+        del w
     res = {}
     for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16), ("f16", torch.float16)):
         x = v.to(dt)
@@ -919,20 +944,24 @@ def main():
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one plain device copy of the volume (counter reference)")
     ap.add_argument("--tune", action="store_true",
-                    help="resident / batched / filters: run the autotuner on the ops first and merge its tiles "
-                         "into --tiles")
+                    help="headline / resident / batched / filters: run the autotuner on the ops first and merge "
+                         "its tiles into --tiles")
     ap.add_argument("--tiles", default=TILES, help="tile file of the autotuner (loaded if present)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("CSV_DIR", "COMMAND", "TITLE"),
                     help="print a markdown summary of a rocprofv3 --stats csv run and exit (no GPU)")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "FETCH_CMD", "WRITE_CMD"),
                     help="print the HBM traffic JSON of two rocprofv3 --pmc runs and exit (no GPU)")
+    ap.add_argument("--traffic-kernels", default="resident", choices=["resident", "headline"],
+                    help="ops whose dispatches --traffic-summary reads (resident 1024^3 or headline 2048^3 FP32)")
     args = ap.parse_args()
     if args.stats_summary:
         print(stats_summary(*args.stats_summary), end="")
         return
     if args.traffic_summary:
         fr, wr, fc, wc = args.traffic_summary
-        print(json.dumps(traffic_summary(fr, wr, args.size or 1024, (fc, wc)), indent=1))
+        kern = HEADLINE_KERNELS if args.traffic_kernels == "headline" else RESIDENT_KERNELS
+        size = args.size or (2048 if args.traffic_kernels == "headline" else 1024)
+        print(json.dumps(traffic_summary(fr, wr, size, (fc, wc), kern), indent=1))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs no multi-GPU path (one process, one device). "

@@ -388,6 +388,8 @@ harpia_status harpia_edge3d(const void *in, harpia_dtype in_t, void *out, harpia
     });
 }
 
+static Region whole_region(const void *p, const int64_t *n);
+
 harpia_status harpia_hessian3d(const void *in, harpia_dtype in_t, float *out, const int64_t shape[3],
                                const double sigma[3], double truncate, harpia_border border, const harpia_exec *ex)
 {
@@ -397,6 +399,19 @@ harpia_status harpia_hessian3d(const void *in, harpia_dtype in_t, float *out, co
         check_shape(shape);
         const Stage base = gauss_stage(in_t, HARPIA_F32, sigma, truncate);
         const int64_t nv = voxels(shape);
+        // device-resident float32 volumes with small equal radii: two passes
+        // of three components (one read of the input each)
+        if (in && in_t == HARPIA_F32 && border == HARPIA_BORDER_REFLECT &&
+            !(ex && (ex->flags & HARPIA_F_FORCE_CHUNKED)) && is_device_pointer(in) && is_device_pointer(out)) {
+            check_exec(ex);
+            check_alias(in, nv * 4, out, 6 * nv * 4);
+            hipStream_t s = ex ? static_cast<hipStream_t>(ex->stream) : nullptr;
+            const ChunkArgs a = make_chunk_args(whole_region(in, shape), whole_region(out, shape), shape);
+            if (launch_hessian_fused(a, in_t, sigma, base.r, nv, s)) {
+                check_hip(hipGetLastError(), "kernel launch");
+                return;
+            }
+        }
         static const int pairs[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
         for (int c = 0; c < 6; ++c) {
             int order[3] = {0, 0, 0};

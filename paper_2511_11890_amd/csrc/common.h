@@ -260,6 +260,11 @@ void make_gauss_dtaps3(const double sigma[3], const int radius[3], GaussTaps &t)
 int64_t launch_gauss_sigma3(const void *x, harpia_dtype x_t, const float *g, const int64_t n[3], const GaussTaps &wt,
                             const GaussTaps &dt, hipStream_t s, float *partials);
 int64_t gauss_sigma3_blocks_bound(const int64_t n[3]);
+// The six Hessian components of a dense region in two three-component
+// passes (out, out + cstride, ..., out + 5 cstride: zz, zy, zx, yy, yx, xx);
+// float32 input, equal radii 1..4.  false: not supported (no launch).
+bool launch_hessian_fused(const ChunkArgs &a, harpia_dtype in_t, const double sigma[3], const int r[3],
+                          int64_t cstride, hipStream_t s);
 
 // Launch the Gaussian on one chunk.  Returns false if no kernel handles the
 // dtype pair / radius combination (caller reports UNSUPPORTED).

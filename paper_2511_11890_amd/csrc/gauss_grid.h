@@ -43,12 +43,14 @@ inline FusedGrid fused_grid(const ChunkArgs &a, int R, int64_t capacity, int ran
     return g;
 }
 
+// In-plane offsets of the fused kernels are 32-bit.
+inline bool fused_ok_extent(const ChunkArgs &a) { return a.in_sy * (a.n[1] + 1) < (int64_t)1 << 31; }
+
 inline bool fused_ok(const GaussTaps &t, const ChunkArgs &a)
 {
     if (!(t.r[0] == t.r[1] && t.r[1] == t.r[2])) return false;
     if (t.r[0] < 1 || t.r[0] > kGaussFusedMaxR) return false;
-    // in-plane offsets are 32-bit
-    return a.in_sy * (a.n[1] + 1) < (int64_t)1 << 31;
+    return fused_ok_extent(a);
 }
 
 }  // namespace gauss_detail

@@ -14,7 +14,7 @@
 //        load, converted to f32) -- the global loads of the next slice are
 //        issued before the current slice is filtered, so HBM latency hides
 //        behind the LDS work;
-//     2. y pass from LDS, register-blocked kMY rows per work item;
+//     2. y pass from LDS, register-blocked 4 (r < 5) or 8 rows per work item;
 //     3. x pass from LDS, 4 adjacent columns per thread (b128 LDS reads);
 //     4. z pass in registers: each thread keeps a ring of 2r+1 partial sums
 //        for each of its 4 columns; slice s adds w|s-o| * t to output o for
@@ -43,7 +43,13 @@ namespace gauss_detail {
 
 
 constexpr int kNT = 256;  // threads per workgroup
-constexpr int kMY = 4;    // rows per y-pass work item
+constexpr int kMY = 4;    // rows per y-pass work item (sigma-gradient, Hessian)
+
+// Rows per y-pass work item of the fused Gaussian: 8 for r >= 5 (each item
+// reads 8 + 2r patch values for 8 outputs instead of 4 + 2r for 4, and the
+// larger blocks cut LDS reads per output at the cost of transient
+// registers), 4 below.
+constexpr int fused_my(int r) { return r >= 5 ? 8 : 4; }
 
 
 static_assert(kTX / 4 * kTY == kNT, "x pass maps one 4-column quad per thread");
@@ -143,7 +149,8 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const FusedTaps &
     constexpr int PSZ = PW * PH;
     constexpr int NLD = (PSZ + NT - 1) / NT;
     constexpr int QP = (PW + 3) & ~3;  // y-pass output pitch, 16-byte rows
-    constexpr int NYI = PW * (kTY / kMY);
+    constexpr int MY = fused_my(R);
+    constexpr int NYI = PW * (kTY / MY);
     constexpr int NH = 4 + 2 * R;  // x-pass inputs per quad
     constexpr int NH4 = (NH + 3) / 4;
     constexpr int QSZ = kTY * QP + 4 * NH4;
@@ -298,11 +305,11 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const FusedTaps &
                     const int it = ytid + itk * NT;
                     if (itk == (NYI + NT - 1) / NT - 1 && it >= NYI) continue;
                     const int col = it % PW, rg = it / PW;
-                    float v[kMY + 2 * R];
+                    float v[MY + 2 * R];
 #pragma unroll
-                    for (int j = 0; j < kMY + 2 * R; ++j) v[j] = p[(rg * kMY + j) * PW + col];
+                    for (int j = 0; j < MY + 2 * R; ++j) v[j] = p[(rg * MY + j) * PW + col];
 #pragma unroll
-                    for (int m = 0; m < kMY; ++m) {
+                    for (int m = 0; m < MY; ++m) {
                         float sacc;
                         if constexpr (PAR & 2) {
                             sacc = 0.f;
@@ -313,7 +320,7 @@ __device__ __forceinline__ void gauss_tile(const ChunkArgs &a, const FusedTaps &
 #pragma unroll
                             for (int k = 1; k <= R; ++k) sacc = fmaf(wy[k], v[m + R - k] + v[m + R + k], sacc);
                         }
-                        q[(rg * kMY + m) * QP + col] = sacc;
+                        q[(rg * MY + m) * QP + col] = sacc;
                     }
                 }
                 // stage slice i + 1 and refill its slot with slice i + 1 + D

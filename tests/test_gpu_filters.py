@@ -242,6 +242,18 @@ def test_hessian_u16_and_chunked(dev):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("sigma", [0.4, 0.7, 1.0, 1.3, (1.0, 0.9, 1.1)])
+def test_hessian_two_pass_equals_six_passes(dev, sigma):
+    # device-resident float32 with radii <= 4 runs two three-component
+    # passes; the chunked device path runs the six one-component passes: the
+    # per-voxel arithmetic is the same sequence, so the results are equal
+    x = torch.from_numpy(phantoms.porous((23, 70, 150), seed=106).numpy()).to(dev)
+    a = h.hessian(x, sigma)
+    b = h.hessian(x, sigma, ex=h.Exec(force_chunked=True, chunk=(0, 0, 0), budget=1 << 30))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 # -------------------------------------------------------- local thresholds
 # The decision v > T is taken in FP32 on the GPU and in FP64 by the oracle:
 # the two must agree wherever |v - T| exceeds the FP32 error bound of T
