@@ -1,0 +1,8 @@
+// Binary erosion / dilation kernels instantiated for uint16_t input.
+#include "morph_impl.h"
+
+namespace harpia {
+namespace morph_detail {
+template bool bits_run<uint16_t>(int, int, bool, const ChunkArgs &, const MorphSpec &, const Out2 &, float, hipStream_t);
+}  // namespace morph_detail
+}  // namespace harpia

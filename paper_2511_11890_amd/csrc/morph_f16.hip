@@ -1,6 +1,10 @@
-// Erosion / dilation kernels instantiated for _Float16 input.
+// Erosion / dilation kernels (grayscale) instantiated for _Float16 input.
 #include "morph_impl.h"
 
 namespace harpia {
+namespace morph_detail {
+extern template bool bits_run<_Float16>(int, int, bool, const ChunkArgs &, const MorphSpec &, const Out2 &, float,
+                                 hipStream_t);
+}  // namespace morph_detail
 template bool morph_run<_Float16>(const ChunkArgs &, const MorphSpec &, bool, const Region *, float, hipStream_t);
 }  // namespace harpia

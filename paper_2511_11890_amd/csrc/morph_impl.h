@@ -347,7 +347,10 @@ __global__ __launch_bounds__(kGNT) void gray_batched_kernel(BatchDesc d, float s
 //
 // A wave owns a strip of kBX = 64 output columns and streams along z; lane l
 // holds input row y_w - R + l of the strip (64 rows: the wave's 64 - 2R
-// output rows plus R halo rows on each side), four waves stack in y.  A row
+// output rows plus R halo rows on each side).  The four waves of a workgroup
+// take four neighbouring strips of the same rows, so that the bytes of a
+// row they read and write (a whole 256-voxel span) share cache lines at the
+// same time.  A row
 // of a slice is one 64-bit mask (bit i: voxel x0 + i is set) plus the 4
 // voxels on each side (enough for R <= 4).  Dilation:
 //   x runs      D_h = OR over |k| <= h of the row shifted by k (mask shifts
@@ -418,6 +421,35 @@ __device__ __forceinline__ void group_set(Group4<Tin> &g, int j, Tin v)
     __builtin_memcpy(reinterpret_cast<char *>(g.w) + j * sizeof(Tin), &v, sizeof(Tin));
 }
 
+// Bits of a group of 4 voxels (bit k: voxel k) that lies wholly inside the
+// read window: v > thr_i for integer inputs (thr_i the threshold's floor, so
+// the comparison is exact), v > thr for float inputs, or v != 0.
+template <typename Tin>
+__device__ __forceinline__ uint32_t group_bits(const Group4<Tin> &g, float thr, int thr_i, bool use_thr)
+{
+    uint32_t nib = 0;
+    if constexpr (std::is_same<Tin, uint8_t>::value) {
+        const uint32_t w = g.w[0];
+        if (!use_thr) {
+            // bit 7 of each byte: byte != 0; then gather bits 7, 15, 23, 31
+            const uint32_t t = ((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w;
+            return (((t >> 7) & 0x01010101u) * 0x01020408u) >> 24;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nib |= (((int)((w >> (8 * k)) & 0xffu) > thr_i) ? 1u : 0u) << k;
+    } else if constexpr (std::is_same<Tin, uint16_t>::value) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int v = (int)((g.w[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+            nib |= ((use_thr ? v > thr_i : v != 0) ? 1u : 0u) << k;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nib |= binarise(group_elem<Tin>(g, k), thr, use_thr) << k;
+    }
+    return nib;
+}
+
 // 16 output bytes (voxel order) from 16 bits.
 __device__ __forceinline__ uint4 bits_to_bytes16(uint32_t b)
 {
@@ -439,7 +471,9 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
     constexpr int NM = BOTH ? 2 : 1;  // pipeline m = 0: dilation of b (BOTH) or of b ^ flip; m = 1: of ~b
     constexpr int YR = bits_rows<R>();
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index is uniform across a wave: keep it (and the strip's
+    // window tests) in scalar registers
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = (int)(b % (uint32_t)tiles_x);
     const int by = (int)((b / (uint32_t)tiles_x) % (uint32_t)tiles_y);
@@ -447,11 +481,11 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
 
     const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1], zbeg = a.out_o[0];
     const int64_t xend = xbeg + a.out_e[2], yend = ybeg + a.out_e[1], zend = zbeg + a.out_e[0];
-    const int64_t x0 = xbeg + (int64_t)bx * kBX;
-    const int64_t yw = ybeg + ((int64_t)by * 4 + wave) * YR;  // first output row of this wave
+    const int64_t x0 = xbeg + ((int64_t)bx * 4 + wave) * kBX;
+    const int64_t yw = ybeg + (int64_t)by * YR;  // first output row of this wave
     const int64_t zo0 = zbeg + (int64_t)bz * zlen;
     const int64_t zo1 = min(zo0 + (int64_t)zlen, zend);
-    if (zo0 >= zo1 || yw >= yend) return;
+    if (zo0 >= zo1 || x0 >= xend) return;
 
     // window of voxels that may be read: the volume, within R of the output
     // region
@@ -470,6 +504,7 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
 
     const int64_t s0 = zo0 - R;
     const int nsteps = (int)(zo1 - zo0) + 2 * R;
+    const int thr_i = (int)thr;  // integer inputs: thr is the threshold's floor
 
     Group4<Tin> raw[kBG];
     auto fetch = [&](int j) __attribute__((always_inline)) {
@@ -500,9 +535,13 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
         for (int g = 0; g < kBG; ++g) {
             const int64_t xg = x0 - 4 + 4 * g;
             uint32_t nib = 0;
+            if (in_x(xg) && in_x(xg + 3)) {
+                nib = group_bits<Tin>(raw[g], thr, thr_i, use_thr);
+            } else {
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (in_x(xg + k)) nib |= binarise(group_elem<Tin>(raw[g], k), thr, use_thr) << k;
+                for (int k = 0; k < 4; ++k)
+                    if (in_x(xg + k)) nib |= binarise(group_elem<Tin>(raw[g], k), thr, use_thr) << k;
+            }
             if (g == 0)
                 hl = nib;
             else if (g == kBG - 1)
@@ -684,25 +723,54 @@ __global__ __launch_bounds__(256) void morph_generic_kernel(ChunkArgs a, Out2 o2
 namespace morph_detail {
 
 template <typename T, int SE, int R, bool BOTH>
+void launch_bits(const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float thr_f, hipStream_t s)
+{
+    static const int64_t cap = resident_blocks(bits_kernel<T, SE, R, BOTH>, kBNT);
+    Tile t;
+    // the kernel generation is part of the key: z splits tuned for other
+    // kernels do not carry over
+    const bool tuned = tune_lookup(TF_BINARY, tune_key_volume(TF_BINARY, R * 4 + SE * 2 + (BOTH ? 1 : 0),
+                                                              tune_type_code<T>() + 16, a.out_e),
+                                   t);
+    const Grid g = make_grid(a, 4 * kBX, bits_rows<R>(), R, cap, tuned ? t.tz : 0);
+    // 4-voxel input groups and 16-byte output rows are aligned?
+    const int vec_in = ((uintptr_t)a.in % (4 * sizeof(T)) == 0) && a.in_sy % 4 == 0 && a.in_sz % 4 == 0 &&
+                       (a.out_o[2] - a.in_o[2]) % 4 == 0;
+    int vec_out = ((uintptr_t)a.out % 16 == 0) && a.out_sy % 16 == 0 && a.out_sz % 16 == 0;
+    if (BOTH) vec_out = vec_out && ((uintptr_t)o2.ptr % 16 == 0) && o2.sy % 16 == 0 && o2.sz % 16 == 0;
+    hipLaunchKernelGGL((bits_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kBNT), 0, s, a, o2,
+                       (uint32_t)(m.op == 0 ? 1u : 0u), thr_f, (int)m.has_threshold, vec_in, vec_out, g.tiles_x,
+                       g.tiles_y, g.zlen);
+}
+
+// The binary kernels of one input type (every element, radius and output
+// form): a function of its own, so that they compile in their own unit.
+template <typename T>
+bool bits_run(int r, int se, bool both, const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float thr_f,
+              hipStream_t s)
+{
+#define HARPIA_BITS(SE_, BOTH_)                                                     \
+    switch (r) {                                                                    \
+    case 1: launch_bits<T, SE_, 1, BOTH_>(a, m, o2, thr_f, s); return true;         \
+    case 2: launch_bits<T, SE_, 2, BOTH_>(a, m, o2, thr_f, s); return true;         \
+    case 3: launch_bits<T, SE_, 3, BOTH_>(a, m, o2, thr_f, s); return true;         \
+    case 4: launch_bits<T, SE_, 4, BOTH_>(a, m, o2, thr_f, s); return true;         \
+    default: return false;                                                          \
+    }
+    if (se == HARPIA_SE_BOX) {
+        if (both) { HARPIA_BITS(HARPIA_SE_BOX, true) }
+        HARPIA_BITS(HARPIA_SE_BOX, false)
+    }
+    if (both) { HARPIA_BITS(HARPIA_SE_BALL, true) }
+    HARPIA_BITS(HARPIA_SE_BALL, false)
+#undef HARPIA_BITS
+}
+
+template <typename T, int SE, int R, bool BOTH>
 void launch_fast(const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float thr_f, hipStream_t s)
 {
     if (m.binary) {
-        static const int64_t cap = resident_blocks(bits_kernel<T, SE, R, BOTH>, kBNT);
-        Tile t;
-        // the kernel generation is part of the key: z splits tuned for other
-        // kernels do not carry over
-        const bool tuned = tune_lookup(TF_BINARY, tune_key_volume(TF_BINARY, R * 4 + SE * 2 + (BOTH ? 1 : 0),
-                                                                  tune_type_code<T>() + 16, a.out_e),
-                                       t);
-        const Grid g = make_grid(a, kBX, 4 * bits_rows<R>(), R, cap, tuned ? t.tz : 0);
-        // 4-voxel input groups and 16-byte output rows are aligned?
-        const int vec_in = ((uintptr_t)a.in % (4 * sizeof(T)) == 0) && a.in_sy % 4 == 0 && a.in_sz % 4 == 0 &&
-                           (a.out_o[2] - a.in_o[2]) % 4 == 0;
-        int vec_out = ((uintptr_t)a.out % 16 == 0) && a.out_sy % 16 == 0 && a.out_sz % 16 == 0;
-        if (BOTH) vec_out = vec_out && ((uintptr_t)o2.ptr % 16 == 0) && o2.sy % 16 == 0 && o2.sz % 16 == 0;
-        hipLaunchKernelGGL((bits_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kBNT), 0, s, a, o2,
-                           (uint32_t)(m.op == 0 ? 1u : 0u), thr_f, (int)m.has_threshold, vec_in, vec_out,
-                           g.tiles_x, g.tiles_y, g.zlen);
+        bits_run<T>(R, SE, BOTH, a, m, o2, thr_f, s);
     } else {
         static const int64_t cap = resident_blocks(gray_kernel<T, SE, R, BOTH>, gray_nt(R));
         Tile t;
