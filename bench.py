@@ -132,10 +132,28 @@ def _short(name: str) -> str:
 
 
 def stats_summary(root: str, command: str, title: str) -> str:
-    """Markdown table of a `rocprofv3 --kernel-trace --stats --output-format
-    csv` run (its kernel_stats.csv under `root`)."""
+    """Markdown tables of a `rocprofv3 --kernel-trace --stats --output-format
+    csv` run under `root`: the library's kernels per (kernel, grid size) from
+    kernel_trace.csv (one row per launch shape, so launches of different
+    volume sizes are not averaged together), then the kernel_stats.csv
+    summary of every kernel the command ran."""
     lines = ["# %s" % title, "", "command: `%s`" % command, "",
-             "| kernel | calls | avg us | min us | max us | total ms | % |", "|---|---|---|---|---|---|---|"]
+             "## Library kernels per launch shape", "",
+             "| kernel | grid (threads) | workgroup | calls | avg us | min us | max us |",
+             "|---|---|---|---|---|---|---|"]
+    groups = {}
+    for row in _csv_rows(root, "kernel_trace.csv"):
+        name = _short(row["Kernel_Name"])
+        if "harpia" not in name:
+            continue
+        key = (name, int(row["Grid_Size_X"]) * int(row["Grid_Size_Y"]) * int(row["Grid_Size_Z"]),
+               int(row["Workgroup_Size_X"]) * int(row["Workgroup_Size_Y"]) * int(row["Workgroup_Size_Z"]))
+        groups.setdefault(key, []).append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
+    for (name, grid, wg), d in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        lines.append("| %s | %d | %d | %d | %.1f | %.1f | %.1f |" % (name, grid, wg, len(d), sum(d) / len(d), min(d),
+                                                                      max(d)))
+    lines += ["", "## All kernels (rocprofv3 --stats)", "",
+              "| kernel | calls | avg us | min us | max us | total ms | % |", "|---|---|---|---|---|---|---|"]
     for row in _csv_rows(root, "kernel_stats.csv"):
         lines.append("| %s | %s | %.1f | %.1f | %.1f | %.2f | %.1f |" % (
             _short(row["Name"]), row["Calls"], float(row["AverageNs"]) / 1e3, float(row["MinNs"]) / 1e3,
@@ -915,20 +933,23 @@ def run_filters(args):
     if not args.no_cpu:
         import oracle
 
-        sl = v[:32].double().cpu().numpy()
-        t0 = time.perf_counter()
-        oracle.mean3d(sl, 1, method="separable")
-        oracle.mean3d(sl, 2, method="separable")
-        oracle.unsharp3d(sl, 2.0, 1.0)
-        oracle.edge3d(sl, "sobel")
-        oracle.hessian3d(sl, 1.0)
-        oracle.local_threshold3d(sl, "niblack", 2, k=-0.2)
-        dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": round(11 * sl.size / dt / 1e9, 6), "unit": "GVox/s",
-                                "cores": oracle.num_threads(), "kind": "oracle",
-                                "sample": "%dx%dx%d slab: separable FP64 mean r=1,2 + unsharp (direct FP64 Gaussian) "
-                                          "sigma 2 + direct FP64 Sobel + direct FP64 Hessian sigma 1 + Niblack r=2, %.1f s"
-                                          % (sl.shape + (dt,))}
+        sa = v[:8].double().cpu().numpy()
+        so = v[:1].double().cpu().numpy()
+
+        def work(sl):
+            oracle.mean3d(sl, 1, method="separable")
+            oracle.mean3d(sl, 2, method="separable")
+            oracle.unsharp3d(sl, 2.0, 1.0)
+            oracle.edge3d(sl, "sobel")
+            oracle.hessian3d(sl, 1.0)
+            oracle.local_threshold3d(sl, "niblack", 2, k=-0.2)
+            return sl.size
+
+        what = "slab: separable FP64 mean r=1,2 + unsharp (direct FP64 Gaussian) sigma 2 + direct FP64 Sobel + " \
+               "direct FP64 Hessian sigma 1 + Niblack r=2"
+        line["cpu_baseline"] = oracle_protocol(lambda: work(sa), lambda: work(so), 11,
+                                               "%dx%dx%d %s" % (sa.shape + (what,)),
+                                               "%dx%dx%d %s" % (so.shape + (what,)))
     return line
 
 
