@@ -415,6 +415,22 @@ __device__ __forceinline__ void group_load4(Group4<Tin> &g, const Tin *p)
     }
 }
 
+// Elements j, j + 1 of a group from one load (2-element alignment).
+template <typename Tin>
+__device__ __forceinline__ void group_load2(Group4<Tin> &g, int j, const Tin *p)
+{
+    if constexpr (sizeof(Tin) == 1) {
+        const uint16_t t = *reinterpret_cast<const uint16_t *>(p);
+        __builtin_memcpy(reinterpret_cast<char *>(g.w) + j, &t, 2);
+    } else if constexpr (sizeof(Tin) == 2) {
+        g.w[j >> 1] = *reinterpret_cast<const uint32_t *>(p);
+    } else {
+        const uint2 t = *reinterpret_cast<const uint2 *>(p);
+        g.w[j] = t.x;
+        g.w[j + 1] = t.y;
+    }
+}
+
 template <typename Tin>
 __device__ __forceinline__ void group_set(Group4<Tin> &g, int j, Tin v)
 {
@@ -514,8 +530,11 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
 #pragma unroll
         for (int g = 0; g < kBG; ++g) {
             const int64_t xg = x0 - 4 + 4 * g;
-            if (vec_in && in_x(xg) && in_x(xg + 3)) {
+            if (vec_in == 4 && in_x(xg) && in_x(xg + 3)) {
                 group_load4<Tin>(raw[g], p + xg);
+            } else if (vec_in == 2 && in_x(xg) && in_x(xg + 3)) {
+                group_load2<Tin>(raw[g], 0, p + xg);
+                group_load2<Tin>(raw[g], 2, p + xg + 2);
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
@@ -574,9 +593,19 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
     uint8_t *outp = static_cast<uint8_t *>(a.out) + (y - ybeg) * a.out_sy + (x0 - xbeg);
     uint8_t *outp2 = BOTH ? static_cast<uint8_t *>(o2.ptr) + (y - ybeg) * o2.sy + (x0 - xbeg) : nullptr;
     auto emit = [&](uint8_t *p, uint64_t v) __attribute__((always_inline)) {
-        if (vec_out && nx_out >= kBX) {
+        if (vec_out == 16 && nx_out >= kBX) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) reinterpret_cast<uint4 *>(p)[q] = bits_to_bytes16((uint32_t)(v >> (16 * q)));
+        } else if (vec_out == 4 && nx_out >= kBX) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint4 b4 = bits_to_bytes16((uint32_t)(v >> (16 * q)));
+                uint32_t *p4 = reinterpret_cast<uint32_t *>(p) + 4 * q;
+                p4[0] = b4.x;
+                p4[1] = b4.y;
+                p4[2] = b4.z;
+                p4[3] = b4.w;
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < kBX; ++i)
@@ -733,11 +762,20 @@ void launch_bits(const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float t
                                                               tune_type_code<T>() + 16, a.out_e),
                                    t);
     const Grid g = make_grid(a, 4 * kBX, bits_rows<R>(), R, cap, tuned ? t.tz : 0);
-    // 4-voxel input groups and 16-byte output rows are aligned?
-    const int vec_in = ((uintptr_t)a.in % (4 * sizeof(T)) == 0) && a.in_sy % 4 == 0 && a.in_sz % 4 == 0 &&
-                       (a.out_o[2] - a.in_o[2]) % 4 == 0;
-    int vec_out = ((uintptr_t)a.out % 16 == 0) && a.out_sy % 16 == 0 && a.out_sz % 16 == 0;
-    if (BOTH) vec_out = vec_out && ((uintptr_t)o2.ptr % 16 == 0) && o2.sy % 16 == 0 && o2.sz % 16 == 0;
+    // Widest aligned access: input groups of 4 or 2 elements (a chain's
+    // intermediate region can start 2 voxels off), output rows of 16 or 4
+    // bytes (the intermediate's pitch is the core plus a halo).
+    auto in_al = [&](int64_t e) {
+        return ((uintptr_t)a.in % (e * sizeof(T)) == 0) && a.in_sy % e == 0 && a.in_sz % e == 0 &&
+               (a.out_o[2] - a.in_o[2]) % e == 0;
+    };
+    const int vec_in = in_al(4) ? 4 : (in_al(2) ? 2 : 1);
+    auto out_al = [&](int64_t e) {
+        bool ok = ((uintptr_t)a.out % e == 0) && a.out_sy % e == 0 && a.out_sz % e == 0;
+        if (BOTH) ok = ok && ((uintptr_t)o2.ptr % e == 0) && o2.sy % e == 0 && o2.sz % e == 0;
+        return ok;
+    };
+    const int vec_out = out_al(16) ? 16 : (out_al(4) ? 4 : 1);
     hipLaunchKernelGGL((bits_kernel<T, SE, R, BOTH>), dim3((uint32_t)g.blocks), dim3(kBNT), 0, s, a, o2,
                        (uint32_t)(m.op == 0 ? 1u : 0u), thr_f, (int)m.has_threshold, vec_in, vec_out, g.tiles_x,
                        g.tiles_y, g.zlen);
