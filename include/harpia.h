@@ -280,7 +280,9 @@ harpia_status harpia_edge3d(const void *in, harpia_dtype in_t, void *out,
 
 /* Erosion (min over the structuring element placed at each voxel) and
  * dilation (max) (Section III-C, label editing module).
- * t: dtype of `in`.  Grayscale: out has dtype t, results are exact.
+ * t: dtype of `in`.  Grayscale: out has dtype t, results are exact; min
+ * and max follow the IEEE 754 totalOrder of the values (-0 < +0, a NaN
+ * orders beyond the infinities on the side of its sign).
  * Binary: if `threshold` is not NaN the input is binarised as in > threshold
  * (strict; the comparison is exact in the input's type), else with
  * HARPIA_F_BINARY as in != 0; `out` is then uint8 {0, 1}.

@@ -10,9 +10,12 @@
 //
 // Single-op kernels compute a dilation; an erosion is the dilation of the
 // negated input, negated back (exact for every dtype: negation is exact in
-// f32 and all u8/u16/f16/bf16 values are f32 values).  Binary erosion is the
-// complement of the dilation of the complement.  "Both" kernels return the
-// erosion and the dilation from one read of the input.
+// f32 and all u8/u16/f16/bf16 values are f32 values; the fast grayscale
+// kernels complement the order keys instead, which is the same reversal).
+// Binary erosion is the complement of the dilation of the complement.
+// "Both" kernels return the erosion and the dilation from one read of the
+// input.  Grayscale extrema follow the IEEE 754 totalOrder of the values
+// (order_key).
 //
 // Structure (same skeleton as the fused Gaussian): a 256-thread workgroup
 // owns a tile of output columns and streams along z.  Per input slice:
@@ -106,6 +109,19 @@ constexpr int kGTX = 64, kGTY = 16;
 constexpr int kGC = 2;                            // output columns per thread
 constexpr int kGNT = (kGTX / kGC) * kGTY;         // threads per workgroup
 
+// Order-preserving map of a float to a signed int: the bit pattern with the
+// 31 value bits inverted when the sign bit is set, so that int order is the
+// IEEE 754 totalOrder of the values (-0 < +0, NaNs beyond the infinities by
+// their sign).  The map is its own inverse.  Grayscale extrema are taken on
+// these keys: integer min / max are exact like the float ones and, unlike
+// them, need no quieting of signalling NaNs before every operation.
+__device__ __forceinline__ int order_key(float x)
+{
+    const int b = __float_as_int(x);
+    return b ^ (int)((uint32_t)(b >> 31) >> 1);
+}
+__device__ __forceinline__ float order_value(int k) { return __int_as_float(k ^ (int)((uint32_t)(k >> 31) >> 1)); }
+
 // Second output of the "both" kernels.
 struct Out2 {
     void *ptr;
@@ -129,11 +145,14 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
     constexpr int NM = BOTH ? 2 : 1;      // 0: max (dilation), 1: min
     constexpr int BUF = PH * PWP + 4 * NV4;
 
-    // Double-buffered patch: slice i is staged into sP[i & 1] while other
-    // threads may still read slice i - 1 from the other half, so one barrier
-    // per slice suffices.  Every thread derives the x-runs it needs straight
-    // from the patch (no intermediate LDS arrays).
-    __shared__ __attribute__((aligned(16))) float sP[2 * BUF];
+    // Double-buffered patch of order keys: slice i is staged into sP[i & 1]
+    // while other threads may still read slice i - 1 from the other half, so
+    // one barrier per slice suffices.  Every thread derives the x-runs it
+    // needs straight from the patch (no intermediate LDS arrays).  A
+    // single-op erosion stages the complemented keys (which reverse the
+    // order) and takes maxima.
+    __shared__ __attribute__((aligned(16))) int sP[2 * BUF];
+    const int flip = (!BOTH && sign < 0.f) ? -1 : 0;
 
     const int tid = threadIdx.x;
     const int64_t xbeg = a.out_o[2], ybeg = a.out_o[1];
@@ -186,13 +205,13 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
     T *outp = static_cast<T *>(a.out) + (gy_out - ybeg) * a.out_sy + (gx_out - xbeg);
     T *outp2 = BOTH ? static_cast<T *>(o2.ptr) + (gy_out - ybeg) * o2.sy + (gx_out - xbeg) : nullptr;
 
-    float acc[NM][P][kGC];
+    int acc[NM][P][kGC];
 #pragma unroll
     for (int m = 0; m < NM; ++m)
 #pragma unroll
         for (int j = 0; j < P; ++j)
 #pragma unroll
-            for (int c = 0; c < kGC; ++c) acc[m][j][c] = 0.f;
+            for (int c = 0; c < kGC; ++c) acc[m][j][c] = 0;
 
     fetch(0);
 
@@ -204,12 +223,11 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
             constexpr int u = decltype(U)::value;
             const int i = base + u;
             if (i > nsteps) return;
-            float *buf = sP + (i & 1) * BUF;
+            int *buf = sP + (i & 1) * BUF;
             if (i < nsteps) {
 #pragma unroll
                 for (int k = 0; k < NLD; ++k)
-                    if (k < NLD - 1 || tid + k * NT < PSZ)
-                        buf[lds[k]] = BOTH ? to_f32(pf[k]) : sign * to_f32(pf[k]);
+                    if (k < NLD - 1 || tid + k * NT < PSZ) buf[lds[k]] = order_key(to_f32(pf[k])) ^ flip;
                 fetch(i + 1);
             }
             if (i >= 1 && i - 1 >= 2 * R && nvalid > 0) {
@@ -220,13 +238,13 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
 #pragma unroll
                     for (int q = 0; q < kGC; ++q)
                         if (q < nvalid) {
-                            outp[zl * a.out_sz + q] = from_f32<T>(acc[1][sl][q]);
-                            outp2[zl * o2.sz + q] = from_f32<T>(acc[0][sl][q]);
+                            outp[zl * a.out_sz + q] = from_f32<T>(order_value(acc[1][sl][q]));
+                            outp2[zl * o2.sz + q] = from_f32<T>(order_value(acc[0][sl][q]));
                         }
                 } else {
 #pragma unroll
                     for (int q = 0; q < kGC; ++q)
-                        if (q < nvalid) outp[zl * a.out_sz + q] = from_f32<T>(sign * acc[0][sl][q]);
+                        if (q < nvalid) outp[zl * a.out_sz + q] = from_f32<T>(order_value(acc[0][sl][q] ^ flip));
                 }
             }
             if (i >= nsteps) return;
@@ -234,35 +252,35 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
 
             // In-plane disc of every z-class (kGC columns): rows dy = -R .. R,
             // each row's x-runs of the half-widths its classes take.
-            float disc[NM][S::NC][kGC];
+            int disc[NM][S::NC][kGC];
             static_for<P>([&](auto DY) {
                 constexpr int dy = decltype(DY)::value - R;
                 constexpr int hmax = S::max_hw(dy);
                 if constexpr (hmax >= 0) {
-                    float v[NV4 * 4];
-                    const float *prow = &buf[(qrow + R + dy) * PWP + qcol];
+                    int v[NV4 * 4];
+                    const int *prow = &buf[(qrow + R + dy) * PWP + qcol];
                     if constexpr (kGC % 4 == 0) {
-                        const float4 *p4 = reinterpret_cast<const float4 *>(prow);
+                        const int4 *p4 = reinterpret_cast<const int4 *>(prow);
 #pragma unroll
                         for (int j = 0; j < NV4; ++j) {
-                            const float4 t4 = p4[j];
+                            const int4 t4 = p4[j];
                             v[4 * j] = t4.x;
                             v[4 * j + 1] = t4.y;
                             v[4 * j + 2] = t4.z;
                             v[4 * j + 3] = t4.w;
                         }
                     } else {
-                        const float2 *p2 = reinterpret_cast<const float2 *>(prow);
+                        const int2 *p2 = reinterpret_cast<const int2 *>(prow);
 #pragma unroll
                         for (int j = 0; j < 2 * NV4; ++j) {
-                            const float2 t2 = p2[j];
+                            const int2 t2 = p2[j];
                             v[2 * j] = t2.x;
                             v[2 * j + 1] = t2.y;
                         }
                     }
 #pragma unroll
                     for (int m = 0; m < NM; ++m) {
-                        float run[kGC];
+                        int run[kGC];
 #pragma unroll
                         for (int q = 0; q < kGC; ++q) run[q] = v[q + R];
                         static_for<hmax + 1>([&](auto H) {
@@ -270,8 +288,8 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
                             if constexpr (h > 0) {
 #pragma unroll
                                 for (int q = 0; q < kGC; ++q)
-                                    run[q] = (m == 0) ? fmaxf(run[q], fmaxf(v[q + R - h], v[q + R + h]))
-                                                      : fminf(run[q], fminf(v[q + R - h], v[q + R + h]));
+                                    run[q] = (m == 0) ? max(run[q], max(v[q + R - h], v[q + R + h]))
+                                                      : min(run[q], min(v[q + R - h], v[q + R + h]));
                             }
                             static_for<S::NC>([&](auto C) {
                                 constexpr int c = decltype(C)::value;
@@ -280,8 +298,8 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
 #pragma unroll
                                     for (int q = 0; q < kGC; ++q)
                                         disc[m][c][q] = first ? run[q]
-                                                              : ((m == 0) ? fmaxf(disc[m][c][q], run[q])
-                                                                          : fminf(disc[m][c][q], run[q]));
+                                                              : ((m == 0) ? max(disc[m][c][q], run[q])
+                                                                          : min(disc[m][c][q], run[q]));
                                 }
                             });
                         });
@@ -299,8 +317,8 @@ __device__ __forceinline__ void gray_tile(const ChunkArgs &a, const Out2 &o2, fl
 #pragma unroll
                     for (int q = 0; q < kGC; ++q)
                         acc[m][sl][q] = (d == R) ? disc[m][c][q]
-                                                 : ((m == 0) ? fmaxf(acc[m][sl][q], disc[m][c][q])
-                                                             : fminf(acc[m][sl][q], disc[m][c][q]));
+                                                 : ((m == 0) ? max(acc[m][sl][q], disc[m][c][q])
+                                                             : min(acc[m][sl][q], disc[m][c][q]));
                 });
             }
         });
@@ -717,7 +735,7 @@ __global__ __launch_bounds__(256) void morph_generic_kernel(ChunkArgs a, Out2 o2
          id += (int64_t)gridDim.x * blockDim.x) {
         const int64_t x = id % ex, y = (id / ex) % ey, z = id / (ex * ey);
         const int64_t gz = a.out_o[0] + z, gy = a.out_o[1] + y, gx = a.out_o[2] + x;
-        float mx = -INFINITY, mn = INFINITY;
+        int mx = INT32_MIN, mn = INT32_MAX;  // order keys (the centre voxel is always taken)
         for (int dz = -rz; dz <= rz; ++dz) {
             const int64_t zz = gz + dz;
             if (zz < 0 || zz >= a.n[0]) continue;
@@ -729,20 +747,21 @@ __global__ __launch_bounds__(256) void morph_generic_kernel(ChunkArgs a, Out2 o2
                     if (xx < 0 || xx >= a.n[2]) continue;
                     if (se == HARPIA_SE_BALL && dz * dz + dy * dy + dx * dx > rz * rz) continue;
                     const Tin raw = in[(zz - a.in_o[0]) * a.in_sz + (yy - a.in_o[1]) * a.in_sy + (xx - a.in_o[2])];
-                    float v = binary ? (float)(binarise(raw, thr, use_thr) ^ flip) : sign * to_f32(raw);
-                    mx = fmaxf(mx, v);
-                    mn = fminf(mn, v);
+                    const float v = binary ? (float)(binarise(raw, thr, use_thr) ^ flip) : sign * to_f32(raw);
+                    const int k = order_key(v);
+                    mx = max(mx, k);
+                    mn = min(mn, k);
                 }
             }
         }
         Tout *op = static_cast<Tout *>(a.out) + z * a.out_sz + y * a.out_sy + x;
         if (both) {
-            *op = from_f32<Tout>(mn);
-            static_cast<Tout *>(o2.ptr)[z * o2.sz + y * o2.sy + x] = from_f32<Tout>(mx);
+            *op = from_f32<Tout>(order_value(mn));
+            static_cast<Tout *>(o2.ptr)[z * o2.sz + y * o2.sy + x] = from_f32<Tout>(order_value(mx));
         } else if (binary) {
-            *op = from_f32<Tout>((float)((uint32_t)mx ^ flip));
+            *op = from_f32<Tout>((float)((uint32_t)order_value(mx) ^ flip));
         } else {
-            *op = from_f32<Tout>(sign * mx);
+            *op = from_f32<Tout>(sign * order_value(mx));
         }
     }
 }
