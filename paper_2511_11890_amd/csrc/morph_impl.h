@@ -721,8 +721,9 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
 
 // Any radii (anisotropic boxes, radii beyond the fast kernels): direct
 // extremum over the element, skipping offsets outside the volume (equal to
-// the reflect boundary for these elements).  mode 0: dilation (or erosion of
-// sign-flipped data), 2: both.
+// the reflect boundary for these elements).  Grayscale: both extrema are
+// kept as order keys; a single op returns the minimum (sign < 0: erosion)
+// or the maximum.  Binary: the dilation of the (possibly complemented) bits.
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(256) void morph_generic_kernel(ChunkArgs a, Out2 o2, int se, int rz, int ry, int rx,
                                                             int both, float sign, int binary, float thr,
@@ -747,7 +748,7 @@ __global__ __launch_bounds__(256) void morph_generic_kernel(ChunkArgs a, Out2 o2
                     if (xx < 0 || xx >= a.n[2]) continue;
                     if (se == HARPIA_SE_BALL && dz * dz + dy * dy + dx * dx > rz * rz) continue;
                     const Tin raw = in[(zz - a.in_o[0]) * a.in_sz + (yy - a.in_o[1]) * a.in_sy + (xx - a.in_o[2])];
-                    const float v = binary ? (float)(binarise(raw, thr, use_thr) ^ flip) : sign * to_f32(raw);
+                    const float v = binary ? (float)(binarise(raw, thr, use_thr) ^ flip) : to_f32(raw);
                     const int k = order_key(v);
                     mx = max(mx, k);
                     mn = min(mn, k);
@@ -761,7 +762,8 @@ __global__ __launch_bounds__(256) void morph_generic_kernel(ChunkArgs a, Out2 o2
         } else if (binary) {
             *op = from_f32<Tout>((float)((uint32_t)order_value(mx) ^ flip));
         } else {
-            *op = from_f32<Tout>(sign * order_value(mx));
+            // grayscale single op: the minimum for an erosion (sign < 0)
+            *op = from_f32<Tout>(order_value(sign < 0.f ? mn : mx));
         }
     }
 }

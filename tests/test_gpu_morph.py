@@ -51,6 +51,51 @@ def test_gray_erode_dilate_bit_exact(dev, dtype, se, r):
     np.testing.assert_array_equal(to_np64(d2), wd)
 
 
+def _order_keys(a):
+    """float32 -> int32 keys whose order is the IEEE 754 totalOrder."""
+    b = a.view(np.int32).astype(np.int64)
+    return np.where(b < 0, b ^ 0x7FFFFFFF, b)
+
+
+def _box_extremum(keys, r, fn):
+    # brute force over the box, offsets outside the volume skipped
+    nz, ny, nx = keys.shape
+    out = np.empty_like(keys)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                out[z, y, x] = fn(keys[max(0, z - r[0]):z + r[0] + 1, max(0, y - r[1]):y + r[1] + 1,
+                                       max(0, x - r[2]):x + r[2] + 1])
+    return out
+
+
+@pytest.mark.parametrize("r", [(1, 1, 1), (2, 2, 2), (1, 2, 0)])
+def test_gray_total_order_of_zeros_and_nans(dev, r):
+    # the header's rule for values float comparison leaves open: -0 < +0,
+    # and NaNs beyond the infinities on the side of their sign; fast
+    # (isotropic) and generic (anisotropic) kernels, single and paired
+    rng = np.random.default_rng(41)
+    v = rng.standard_normal((7, 12, 70)).astype(np.float32)
+    flat = v.reshape(-1)
+    idx = rng.permutation(flat.size)
+    flat[idx[:40]] = 0.0
+    flat[idx[40:80]] = -0.0
+    flat[idx[80:86]] = np.float32(np.inf)
+    flat[idx[86:92]] = np.float32(-np.inf)
+    nan = np.array([0x7FC00000, 0xFFC00000], dtype=np.uint32).view(np.float32)
+    flat[idx[92:95]] = nan[0]
+    flat[idx[95:98]] = nan[1]
+    keys = _order_keys(v)
+    want_e = _box_extremum(keys, r, np.min)
+    want_d = _box_extremum(keys, r, np.max)
+    vd = torch.from_numpy(v).to(dev)
+    e, d = h.erode(vd, "box", r), h.dilate(vd, "box", r)
+    e2, d2 = h.erode_dilate(vd, "box", r)
+    torch.cuda.synchronize()
+    for got, want in ((e, want_e), (d, want_d), (e2, want_e), (d2, want_d)):
+        np.testing.assert_array_equal(_order_keys(got.cpu().numpy()), want)
+
+
 @pytest.mark.parametrize("r", [(1, 2, 3), (0, 0, 2), (3, 0, 1), (0, 0, 0)])
 def test_gray_anisotropic_box_generic_path(dev, r):
     v = _gray((19, 29, 70), torch.float32, seed=12)
