@@ -383,8 +383,8 @@ __global__ __launch_bounds__(kGNT) void gray_batched_kernel(BatchDesc d, float s
 // outside the volume are 0 in the mask that is dilated (for these elements
 // ignoring them is the reflect boundary), and so are voxels farther than R
 // from the output region (no stored output reads them).  No barriers:
-// the waves are independent (1-byte inputs pass through a wave-private LDS
-// block to coalesce their loads).
+// the waves are independent (each has a private LDS block through which its
+// output rows reach coalesced stores).
 // 1 if v counts as set: v > thr (use_thr; thr is the largest value of the
 // input's type not above the threshold, so the comparison is exact) or v != 0.
 template <typename Tin>
@@ -541,91 +541,30 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
     const int nsteps = (int)(zo1 - zo0) + 2 * R;
     const int thr_i = (int)thr;  // integer inputs: thr is the threshold's floor
 
-    // 1-byte inputs are fetched coalesced: load k of lane l takes 4-voxel
-    // group gi = 64 k + l of the wave's block (row gi / kBG, group gi % kBG),
-    // so consecutive lanes read consecutive groups of a row instead of one
-    // group of each of 64 rows, and the block reaches each lane's row
-    // through a wave-private LDS buffer (odd row pitch in words: a lane
-    // reading its own row hits distinct banks).  Wider inputs, and radii
-    // above 2 (whose unrolled slice loop would then hold twice the
-    // registers), load their row's groups directly, one lane per row.
-    constexpr bool kStaged = sizeof(Tin) == 1 && R <= 2;
-    constexpr int kPitch = kBG + 1;  // words per staged row (1-byte inputs)
-    __shared__ uint32_t sB[kStaged ? 4 : 1][kStaged ? 64 * kPitch : 1];
-    uint32_t *blk = sB[kStaged ? wave : 0];
-    // staged fetch: per load, the group's element offset in the slice and
-    // its voxels inside the read window (4 bits; 0: nothing to read)
-    int32_t toff[kStaged ? kBG : 1];
-    uint32_t tnib[kStaged ? (kBG + 7) / 8 : 1];
-    if constexpr (kStaged) {
-#pragma unroll
-        for (int q = 0; q < (kBG + 7) / 8; ++q) tnib[q] = 0;
-#pragma unroll
-        for (int k = 0; k < kBG; ++k) {
-            const int gi = 64 * k + lane;
-            const int row = gi / kBG, g = gi - (gi / kBG) * kBG;
-            const int64_t yy = yw - R + row, xg = x0 - 4 + 4 * g;
-            uint32_t nib = 0;
-            if (yy >= ylo && yy < yhi) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (in_x(xg + q)) nib |= 1u << q;
-            }
-            tnib[k / 8] |= nib << (4 * (k % 8));
-            toff[k] = nib ? (int32_t)((yy - a.in_o[1]) * a.in_sy + (xg - a.in_o[2])) : 0;
-        }
-    }
+    // The wave's LDS block passes each output row from its lane to
+    // coalesced stores: 16 rows of 64 bytes per store instruction instead of
+    // 64 rows of 16 (row pitch of 20 words: b128 writes on distinct banks).
+    constexpr int kOutPitch = 20;
+    __shared__ __attribute__((aligned(16))) uint32_t sB[4][64 * kOutPitch];
+    uint32_t *blk = sB[wave];
     Group4<Tin> raw[kBG];
     auto fetch = [&](int j) __attribute__((always_inline)) {
         const int64_t z = s0 + (j < nsteps ? j : nsteps - 1);
-        if constexpr (kStaged) {
-            if (z < zlo || z >= zhi) return;
-            const Tin *pz = in + (z - a.in_o[0]) * a.in_sz;
+        if (!row_in || z < zlo || z >= zhi) return;
+        const Tin *p = row_base + (z - a.in_o[0]) * a.in_sz;
 #pragma unroll
-            for (int k = 0; k < kBG; ++k) {
-                const uint32_t nib = (tnib[k / 8] >> (4 * (k % 8))) & 15u;
-                if (nib == 15u && vec_in == 4) {
-                    group_load4<Tin>(raw[k], pz + toff[k]);
-                } else if (nib == 15u && vec_in == 2) {
-                    group_load2<Tin>(raw[k], 0, pz + toff[k]);
-                    group_load2<Tin>(raw[k], 2, pz + toff[k] + 2);
-                } else {
+        for (int g = 0; g < kBG; ++g) {
+            const int64_t xg = x0 - 4 + 4 * g;
+            if (vec_in == 4 && in_x(xg) && in_x(xg + 3)) {
+                group_load4<Tin>(raw[g], p + xg);
+            } else if (vec_in == 2 && in_x(xg) && in_x(xg + 3)) {
+                group_load2<Tin>(raw[g], 0, p + xg);
+                group_load2<Tin>(raw[g], 2, p + xg + 2);
+            } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (nib & (1u << q)) group_set<Tin>(raw[k], q, pz[toff[k] + q]);
-                }
+                for (int k = 0; k < 4; ++k)
+                    if (in_x(xg + k)) group_set<Tin>(raw[g], k, p[xg + k]);
             }
-        } else {
-            if (!row_in || z < zlo || z >= zhi) return;
-            const Tin *p = row_base + (z - a.in_o[0]) * a.in_sz;
-#pragma unroll
-            for (int g = 0; g < kBG; ++g) {
-                const int64_t xg = x0 - 4 + 4 * g;
-                if (vec_in == 4 && in_x(xg) && in_x(xg + 3)) {
-                    group_load4<Tin>(raw[g], p + xg);
-                } else if (vec_in == 2 && in_x(xg) && in_x(xg + 3)) {
-                    group_load2<Tin>(raw[g], 0, p + xg);
-                    group_load2<Tin>(raw[g], 2, p + xg + 2);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (in_x(xg + k)) group_set<Tin>(raw[g], k, p[xg + k]);
-                }
-            }
-        }
-    };
-    // staged fetch: the loaded groups into the wave's LDS block (each lane's
-    // row is then read back by pack)
-    auto put = [&]() __attribute__((always_inline)) {
-        if constexpr (kStaged) {
-#pragma unroll
-            for (int k = 0; k < kBG; ++k) {
-                const int gi = 64 * k + lane;
-                blk[gi + gi / kBG] = raw[k].w[0];  // row * kPitch + group
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     };
     // bits of slice j from raw: row mask, left halo (bits 0..3 = x0-4..x0-1),
@@ -638,16 +577,14 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
         if (!row_in || z < zlo || z >= zhi) return false;
 #pragma unroll
         for (int g = 0; g < kBG; ++g) {
-            Group4<Tin> rg = raw[g];
-            if constexpr (kStaged) rg.w[0] = blk[lane * kPitch + g];
             const int64_t xg = x0 - 4 + 4 * g;
             uint32_t nib = 0;
             if (in_x(xg) && in_x(xg + 3)) {
-                nib = group_bits<Tin>(rg, thr, thr_i, use_thr);
+                nib = group_bits<Tin>(raw[g], thr, thr_i, use_thr);
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (in_x(xg + k)) nib |= binarise(group_elem<Tin>(rg, k), thr, use_thr) << k;
+                    if (in_x(xg + k)) nib |= binarise(group_elem<Tin>(raw[g], k), thr, use_thr) << k;
             }
             if (g == 0)
                 hl = nib;
@@ -701,6 +638,31 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
         }
     };
 
+    // Coalesced output of slice zl (whole 64-column strips with 16-byte
+    // aligned rows): every lane puts its row's 64 bytes into the block, then
+    // store k of lane l writes 16 bytes of row (64 k + l) / 4.  Rows that are
+    // halo or past the region are not stored.
+    auto emit_rows = [&](uint8_t *slice, int64_t sy, uint64_t v) __attribute__((always_inline)) {
+        uint4 *mine = reinterpret_cast<uint4 *>(blk + lane * kOutPitch);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mine[q] = bits_to_bytes16((uint32_t)(v >> (16 * q)));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int idx = 64 * k + lane, r = idx >> 2, q = idx & 3;
+            const int64_t yr = yw - R + r;
+            const uint4 b4 = *reinterpret_cast<const uint4 *>(blk + r * kOutPitch + 4 * q);
+            if (r >= R && r < 64 - R && yr < yend)
+                *reinterpret_cast<uint4 *>(slice + (yr - ybeg) * sy + 16 * q) = b4;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    const bool rows_out = vec_out == 16 && nx_out >= kBX;  // uniform per wave
+
     uint64_t acc[NM][P];
 #pragma unroll
     for (int m = 0; m < NM; ++m)
@@ -715,7 +677,6 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
             if (i >= nsteps) return;
             uint64_t row[NM];
             uint32_t hl[NM], hr[NM];
-            put();
             const bool live = pack(i, row[0], hl[0], hr[0]);
             fetch(i + 1);
             // complement within the window (voxels outside stay 0)
@@ -771,16 +732,27 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
                 });
             }
             // output s0 + i - R is complete
-            if (i >= 2 * R && out_row) {
+            if (i >= 2 * R) {
                 constexpr int sl = (u - R + 2 * P) % P;
                 const int64_t o = s0 + i - R;
                 if (o < zo1) {
                     const int64_t zl = o - zbeg;
-                    if constexpr (BOTH) {
-                        emit(outp + zl * a.out_sz, ~acc[1][sl]);  // erosion
-                        emit(outp2 + zl * o2.sz, acc[0][sl]);     // dilation
-                    } else {
-                        emit(outp + zl * a.out_sz, flip ? ~acc[0][sl] : acc[0][sl]);
+                    if (rows_out) {
+                        uint8_t *s1 = static_cast<uint8_t *>(a.out) + zl * a.out_sz + (x0 - xbeg);
+                        if constexpr (BOTH) {
+                            uint8_t *s2 = static_cast<uint8_t *>(o2.ptr) + zl * o2.sz + (x0 - xbeg);
+                            emit_rows(s1, a.out_sy, ~acc[1][sl]);  // erosion
+                            emit_rows(s2, o2.sy, acc[0][sl]);      // dilation
+                        } else {
+                            emit_rows(s1, a.out_sy, flip ? ~acc[0][sl] : acc[0][sl]);
+                        }
+                    } else if (out_row) {
+                        if constexpr (BOTH) {
+                            emit(outp + zl * a.out_sz, ~acc[1][sl]);  // erosion
+                            emit(outp2 + zl * o2.sz, acc[0][sl]);     // dilation
+                        } else {
+                            emit(outp + zl * a.out_sz, flip ? ~acc[0][sl] : acc[0][sl]);
+                        }
                     }
                 }
             }

@@ -86,7 +86,7 @@ def test_budget_error_and_no_leak(dev, vol_u16):
         h.gaussian(x, 2.0, ex=h.Exec(budget=64 << 10))
     assert e.value.status == -3  # HARPIA_ERR_BUDGET
     free1 = torch.cuda.mem_get_info()[0]
-    assert free1 == free0
+    assert free1 >= free0  # nothing left behind (the runtime may release its own buffers meanwhile)
 
 
 @pytest.mark.parametrize("at", [1, 2, 3])
@@ -101,7 +101,7 @@ def test_injected_allocation_failure_frees_everything(dev, vol_u16, at):
         assert e.value.status == -4  # HARPIA_ERR_OOM
     finally:
         del os.environ["HARPIA_TEST_FAIL_ALLOC_AT"]
-    assert torch.cuda.mem_get_info()[0] == free0
+    assert torch.cuda.mem_get_info()[0] >= free0  # nothing left behind
     got = h.gaussian(x, 2.0, ex=h.Exec(budget=4 << 20))  # still works afterwards
     assert got.shape == x.shape
 
@@ -123,4 +123,4 @@ def test_resident_no_device_memory_kept(dev):
         h.gaussian(x, 1.0, out=y)
         h.gaussian(x, (1.0, 0.5, 2.0), out=y)  # unfused: allocates and frees scratch
     torch.cuda.synchronize()
-    assert torch.cuda.mem_get_info()[0] == free0
+    assert torch.cuda.mem_get_info()[0] >= free0  # nothing left behind
