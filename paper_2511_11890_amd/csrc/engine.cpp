@@ -153,6 +153,26 @@ Region dense_region(void *p, const int64_t lo[3], const int64_t hi[3])
     return r;
 }
 
+// Row pitch, in elements, of a chain's intermediate buffer: rows start on
+// 16-byte boundaries (a core plus its halo is rarely a multiple of 16
+// bytes), so the next kernels keep their widest aligned loads and stores.
+// The padding columns are never written or read.
+int64_t inter_pitch(int64_t width, size_t es)
+{
+    const int64_t q = 16 / (int64_t)es;
+    return (width + q - 1) / q * q;
+}
+
+// Region of an intermediate buffer p covering [lo, hi), rows inter_pitch
+// apart.
+Region inter_region(void *p, size_t es, const int64_t lo[3], const int64_t hi[3])
+{
+    Region r = dense_region(p, lo, hi);
+    r.sy = inter_pitch(hi[2] - lo[2], es);
+    r.sz = (hi[1] - lo[1]) * r.sy;
+    return r;
+}
+
 // Region [lo, hi) of a whole volume of extent n stored densely at base.
 Region volume_region(const void *base, size_t es, const int64_t n[3], const int64_t lo[3], const int64_t hi[3])
 {
@@ -209,7 +229,7 @@ void run_chunk_stages(const Job &job, const Region &in, const Region &out, const
             int64_t h[3], lo[3], hi[3];
             tail_halo(job.stages, k, h);
             expand(c0, c1, h, job.n, lo, hi);
-            const Region mid = dense_region(inter[k], lo, hi);
+            const Region mid = inter_region(inter[k], dtype_size(st.out_t), lo, hi);
             launch_stage(st, cur, mid, nullptr, job.n, s, scratch, scratch_bytes);
             cur = mid;
         }
@@ -227,7 +247,10 @@ void chunk_layout(const std::vector<Stage> &st, const int64_t c0[3], const int64
         tail_halo(st, k, h);
         expand(c0, c1, h, n, lo, hi);
         for (int a = 0; a < 3; ++a) ext[a] = hi[a] - lo[a];
-        if (k + 1 < st.size()) inter_bytes[k] = align_up((size_t)vol(ext) * dtype_size(st[k].out_t));
+        if (k + 1 < st.size()) {
+            const size_t es = dtype_size(st[k].out_t);
+            inter_bytes[k] = align_up((size_t)(ext[0] * ext[1] * inter_pitch(ext[2], es)) * es);
+        }
         scratch = std::max(scratch, align_up(stage_scratch(st[k], ext, n)));
     }
 }
@@ -243,7 +266,10 @@ void worst_layout(const std::vector<Stage> &st, const int64_t core[3], const int
         int64_t h[3], ext[3];
         tail_halo(st, k, h);
         for (int a = 0; a < 3; ++a) ext[a] = std::min(n[a], std::min(core[a], n[a]) + 2 * h[a]);
-        if (k + 1 < st.size()) inter_bytes[k] = align_up((size_t)vol(ext) * dtype_size(st[k].out_t));
+        if (k + 1 < st.size()) {
+            const size_t es = dtype_size(st[k].out_t);
+            inter_bytes[k] = align_up((size_t)(ext[0] * ext[1] * inter_pitch(ext[2], es)) * es);
+        }
         scratch = std::max(scratch, align_up(stage_scratch(st[k], ext, n)));
     }
 }
