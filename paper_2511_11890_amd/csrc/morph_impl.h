@@ -548,24 +548,44 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
     __shared__ __attribute__((aligned(16))) uint32_t sB[4][64 * kOutPitch];
     uint32_t *blk = sB[wave];
     Group4<Tin> raw[kBG];
+    auto load_group = [&](const Tin *p, int g) __attribute__((always_inline)) {
+        const int64_t xg = x0 - 4 + 4 * g;
+        if (vec_in >= 4 && in_x(xg) && in_x(xg + 3)) {
+            group_load4<Tin>(raw[g], p + xg);
+        } else if (vec_in == 2 && in_x(xg) && in_x(xg + 3)) {
+            group_load2<Tin>(raw[g], 0, p + xg);
+            group_load2<Tin>(raw[g], 2, p + xg + 2);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (in_x(xg + k)) group_set<Tin>(raw[g], k, p[xg + k]);
+        }
+    };
     auto fetch = [&](int j) __attribute__((always_inline)) {
         const int64_t z = s0 + (j < nsteps ? j : nsteps - 1);
         if (!row_in || z < zlo || z >= zhi) return;
         const Tin *p = row_base + (z - a.in_o[0]) * a.in_sz;
+        if constexpr (sizeof(Tin) <= 2) {
+            // 16-byte aligned rows with the whole 64-voxel core in the
+            // window: the core in 16-byte loads (4 for u8, 8 for 16-bit
+            // types) instead of one load per 4-voxel group
+            if (vec_in == 16 && in_x(x0) && in_x(x0 + kBX - 1)) {
+                constexpr int GW = Group4<Tin>::W;
+                const uint4 *q = reinterpret_cast<const uint4 *>(p + x0);
 #pragma unroll
-        for (int g = 0; g < kBG; ++g) {
-            const int64_t xg = x0 - 4 + 4 * g;
-            if (vec_in == 4 && in_x(xg) && in_x(xg + 3)) {
-                group_load4<Tin>(raw[g], p + xg);
-            } else if (vec_in == 2 && in_x(xg) && in_x(xg + 3)) {
-                group_load2<Tin>(raw[g], 0, p + xg);
-                group_load2<Tin>(raw[g], 2, p + xg + 2);
-            } else {
+                for (int i = 0; i < kBX * (int)sizeof(Tin) / 16; ++i) {
+                    const uint4 t = q[i];
+                    const uint32_t w4[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (in_x(xg + k)) group_set<Tin>(raw[g], k, p[xg + k]);
+                    for (int k = 0; k < 4; ++k) raw[1 + (4 * i + k) / GW].w[(4 * i + k) % GW] = w4[k];
+                }
+                load_group(p, 0);
+                load_group(p, kBG - 1);
+                return;
             }
         }
+#pragma unroll
+        for (int g = 0; g < kBG; ++g) load_group(p, g);
     };
     // bits of slice j from raw: row mask, left halo (bits 0..3 = x0-4..x0-1),
     // right halo (bits 0..3 = x0+64..x0+67); 0 outside the window.  Returns
@@ -826,14 +846,14 @@ void launch_bits(const ChunkArgs &a, const MorphSpec &m, const Out2 &o2, float t
                                                               tune_type_code<T>() + 16, a.out_e),
                                    t);
     const Grid g = make_grid(a, 4 * kBX, bits_rows<R>(), R, cap, tuned ? t.tz : 0);
-    // Widest aligned access: input groups of 4 or 2 elements (a chain's
-    // intermediate region can start 2 voxels off), output rows of 16 or 4
-    // bytes (the intermediate's pitch is the core plus a halo).
+    // Widest aligned access: input rows in 16-byte pieces (1- and 2-byte
+    // types), else groups of 4 or 2 elements (a chain's intermediate region
+    // can start 2 voxels off); output rows of 16 or 4 bytes.
     auto in_al = [&](int64_t e) {
         return ((uintptr_t)a.in % (e * sizeof(T)) == 0) && a.in_sy % e == 0 && a.in_sz % e == 0 &&
                (a.out_o[2] - a.in_o[2]) % e == 0;
     };
-    const int vec_in = in_al(4) ? 4 : (in_al(2) ? 2 : 1);
+    const int vec_in = (sizeof(T) <= 2 && in_al(16 / (int64_t)sizeof(T))) ? 16 : (in_al(4) ? 4 : (in_al(2) ? 2 : 1));
     auto out_al = [&](int64_t e) {
         bool ok = ((uintptr_t)a.out % e == 0) && a.out_sy % e == 0 && a.out_sz % e == 0;
         if (BOTH) ok = ok && ((uintptr_t)o2.ptr % e == 0) && o2.sy % e == 0 && o2.sz % e == 0;
