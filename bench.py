@@ -55,6 +55,8 @@ KERNEL_SOURCES = {
               "paper_2511_11890_amd/csrc/gauss_impl.h", "paper_2511_11890_amd/csrc/gauss_f32.hip"],
     "morph": ["paper_2511_11890_amd/csrc/common.h", "paper_2511_11890_amd/csrc/morph_impl.h",
               "paper_2511_11890_amd/csrc/morph_f32.hip"],
+    "bits": ["paper_2511_11890_amd/csrc/common.h", "paper_2511_11890_amd/csrc/morph_impl.h",
+             "paper_2511_11890_amd/csrc/morph_bits_u8.hip", "paper_2511_11890_amd/csrc/morph_bits_u16.hip"],
 }
 
 # kernel-name fragments of the 2048^3 FP32 ops of the headline step
@@ -63,12 +65,15 @@ HEADLINE_KERNELS = {
     "f32_sigma4": ("gauss", "gauss_fused_kernel<float, float, 12,"),
 }
 
-# kernel-name fragments of the resident workload's ops (f32, fused kernels)
+# kernel-name fragments of the resident workload's ops (fused kernels), with
+# their algorithmic bytes per voxel where the op is not f32 in, f32 out
 RESIDENT_KERNELS = {
     "gauss_s1": ("gauss", "gauss_fused_kernel<float, float, 3,"),
     "gauss_s2": ("gauss", "gauss_fused_kernel<float, float, 6,"),
     "gauss_s4": ("gauss", "gauss_fused_kernel<float, float, 12,"),
     "erode_dilate_ball3": ("morph", "gray_kernel<float, 1, 3, true>"),
+    "bin_u8_box1": ("bits", "bits_kernel<unsigned char, 0, 1, true>", 3),
+    "bin_u16_ball2": ("bits", "bits_kernel<unsigned short, 1, 2, true>", 4),
 }
 
 
@@ -181,8 +186,8 @@ def traffic_summary(fetch_root: str, write_root: str, size: int, commands, kerne
         ref = max(copies)
         scale = copy_kib / ref
         out["copy_ref"][counter] = {"kib": ref, "expected_kib": copy_kib, "scale": round(scale, 4)}
-        for op, (_, pat) in kernels.items():
-            vals = [float(r["Counter_Value"]) for r in rows if pat in r["Kernel_Name"]]
+        for op, spec in kernels.items():
+            vals = [float(r["Counter_Value"]) for r in rows if spec[1] in r["Kernel_Name"]]
             if vals:
                 per_op[op][counter] = (sum(vals) / len(vals), len(vals), scale)
     for op, d in per_op.items():
@@ -191,7 +196,8 @@ def traffic_summary(fetch_root: str, write_root: str, size: int, commands, kerne
         nout = 2 if op.startswith("erode_dilate") else 1
         fetch = d["FETCH_SIZE"][0] * d["FETCH_SIZE"][2] * 1024.0
         write = d["WRITE_SIZE"][0] * d["WRITE_SIZE"][2] * 1024.0
-        alg = 4.0 * vox * (1 + nout)
+        spec = kernels[op]
+        alg = (spec[2] if len(spec) > 2 else 4.0 * (1 + nout)) * vox
         out["ops"][op] = {"fetch_kib_raw": round(d["FETCH_SIZE"][0], 1), "write_kib_raw": round(d["WRITE_SIZE"][0], 1),
                           "dispatches": d["FETCH_SIZE"][1], "hbm_bytes_per_launch": int(fetch + write),
                           "alg_bytes_per_launch": int(alg), "traffic_over_alg": round((fetch + write) / alg, 4)}

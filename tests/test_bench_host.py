@@ -40,15 +40,18 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
     copy_kib = 4.0 * size ** 3 / 1024.0
     k1 = "void harpia::gauss_detail::gauss_fused_kernel<float, float, 3, false, 0, 1>(...)"
     k3 = "void harpia::morph_detail::gray_kernel<float, 1, 3, true>(...)"
+    kb = "void harpia::morph_detail::bits_kernel<unsigned char, 0, 1, true>(...)"
     fetch = [{"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "FETCH_SIZE", "Counter_Value": copy_kib / 2},
              {"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "FETCH_SIZE", "Counter_Value": 3.0},
              {"Kernel_Name": k1, "Counter_Name": "FETCH_SIZE", "Counter_Value": 0.75 * copy_kib},
              {"Kernel_Name": k1, "Counter_Name": "FETCH_SIZE", "Counter_Value": 0.75 * copy_kib},
-             {"Kernel_Name": k3, "Counter_Name": "FETCH_SIZE", "Counter_Value": 0.5 * copy_kib}]
+             {"Kernel_Name": k3, "Counter_Name": "FETCH_SIZE", "Counter_Value": 0.5 * copy_kib},
+             {"Kernel_Name": kb, "Counter_Name": "FETCH_SIZE", "Counter_Value": 0.125 * copy_kib}]
     write = [{"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "WRITE_SIZE", "Counter_Value": copy_kib},
              {"Kernel_Name": k1, "Counter_Name": "WRITE_SIZE", "Counter_Value": copy_kib},
              {"Kernel_Name": k1, "Counter_Name": "WRITE_SIZE", "Counter_Value": copy_kib},
-             {"Kernel_Name": k3, "Counter_Name": "WRITE_SIZE", "Counter_Value": 2 * copy_kib}]
+             {"Kernel_Name": k3, "Counter_Name": "WRITE_SIZE", "Counter_Value": 2 * copy_kib},
+             {"Kernel_Name": kb, "Counter_Name": "WRITE_SIZE", "Counter_Value": 0.5 * copy_kib}]
     _write_counters(str(tmp_path / "f"), fetch)
     _write_counters(str(tmp_path / "w"), write)
     out = bench.traffic_summary(str(tmp_path / "f"), str(tmp_path / "w"), size, ("cf", "cw"))
@@ -63,6 +66,11 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
     e3 = out["ops"]["erode_dilate_ball3"]
     assert e3["alg_bytes_per_launch"] == 12 * size ** 3
     assert e3["traffic_over_alg"] == pytest.approx((1.0 + 2.0) / 3.0)
+    # binary u8 pair: 1 B read, 2 B written per voxel (3 B algorithmic);
+    # the counters read 0.25 x 4 B and 0.5 x 4 B per voxel after scaling
+    b1 = out["ops"]["bin_u8_box1"]
+    assert b1["alg_bytes_per_launch"] == 3 * size ** 3
+    assert b1["traffic_over_alg"] == pytest.approx((1.0 + 2.0) / 3.0)
     # ops without both counters are left out
     assert "gauss_s4" not in out["ops"]
 
