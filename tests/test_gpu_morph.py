@@ -139,6 +139,9 @@ def _binary_case(kind, shape, seed):
     if kind == "u8flag":
         b = (phantoms.porous(shape, seed=seed) > 0.5).to(torch.uint8)
         return b, None, True, to_np64(b)
+    if kind == "u8thr":
+        t = (phantoms.porous_u16(shape, seed=seed).to(torch.int32) >> 8).to(torch.uint8)
+        return t, 127.0, False, oracle.threshold(to_np64(t), 127.0)
     if kind == "f32_nonrep":  # threshold not representable in float32
         v = phantoms.porous(shape, seed=seed)
         thr = 0.5 + 1e-12
@@ -159,6 +162,25 @@ def test_binary_erode_dilate_bit_exact(dev, kind, se, r):
     assert e.dtype == torch.uint8
     we, wd = oracle.erode3d(b, se, r), oracle.dilate3d(b, se, r)
     for got, want in ((e, we), (d, wd), (e2, we), (d2, wd)):
+        np.testing.assert_array_equal(to_np64(got), want)
+
+
+@pytest.mark.parametrize("kind", ["u16", "u8flag", "u8thr"])
+@pytest.mark.parametrize("nx", [336, 208])
+@pytest.mark.parametrize("se,r", [("box", 1), ("ball", 2), ("box", 3), ("ball", 4)])
+def test_binary_aligned_rows_bit_exact(dev, kind, nx, se, r):
+    """Rows that are whole multiples of 16 bytes: strips whose 64-voxel core
+    lies in the read window load it in 16-byte pieces, while the last,
+    partial strip (nx mod 64 = 16) and the halo groups at the x faces take
+    the per-group loads."""
+    t, thr, flag, b = _binary_case(kind, (13, 70, nx), seed=19)
+    td = t.to(dev)
+    print("binary aligned", kind, nx, se, r, flush=True)
+    e = h.erode(td, se, r, threshold=thr, binary=flag)
+    e2, d2 = h.erode_dilate(td, se, r, threshold=thr, binary=flag)
+    torch.cuda.synchronize()
+    we, wd = oracle.erode3d(b, se, r), oracle.dilate3d(b, se, r)
+    for got, want in ((e, we), (e2, we), (d2, wd)):
         np.testing.assert_array_equal(to_np64(got), want)
 
 
