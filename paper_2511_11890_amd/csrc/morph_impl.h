@@ -496,6 +496,15 @@ __device__ __forceinline__ uint4 bits_to_bytes16(uint32_t b)
     return make_uint4(q[0], q[1], q[2], q[3]);
 }
 
+// 16-byte store marked non-temporal: output rows are not read back by the
+// kernel, so they need not displace the input rows from the caches.
+__device__ __forceinline__ void store16_nt(uint8_t *p, uint4 v)
+{
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const v4u t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, reinterpret_cast<v4u *>(p));
+}
+
 template <typename Tin, int SE, int R, bool BOTH>
 __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32_t flip, float thr, int use_thr,
                                                     int vec_in, int vec_out, int tiles_x, int tiles_y, int zlen)
@@ -675,7 +684,7 @@ __global__ __launch_bounds__(kBNT) void bits_kernel(ChunkArgs a, Out2 o2, uint32
             const int64_t yr = yw - R + r;
             const uint4 b4 = *reinterpret_cast<const uint4 *>(blk + r * kOutPitch + 4 * q);
             if (r >= R && r < 64 - R && yr < yend)
-                *reinterpret_cast<uint4 *>(slice + (yr - ybeg) * sy + 16 * q) = b4;
+                store16_nt(slice + (yr - ybeg) * sy + 16 * q, b4);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
