@@ -56,15 +56,18 @@ static_assert(kTX / 4 * kTY == kNT, "x pass maps one 4-column quad per thread");
 
 // Store 4 consecutive outputs: one 16-byte (f32) or 8-byte (16-bit) store
 // when all 4 are inside the region and the address is aligned, else element
-// by element.
+// by element.  The aligned stores are non-temporal: the kernel never reads
+// its output, and streaming it past the caches leaves them to the input
+// slices.
 template <typename T>
 __device__ __forceinline__ void store4(T *p, const float v[4], int nvalid)
 {
     constexpr uintptr_t kAlignMask = sizeof(T) * 4 - 1;
     if (nvalid == 4 && (reinterpret_cast<uintptr_t>(p) & kAlignMask) == 0) {
         if constexpr (sizeof(T) == 4) {
-            float4 q = make_float4(v[0], v[1], v[2], v[3]);
-            *reinterpret_cast<float4 *>(p) = q;
+            typedef float v4f __attribute__((ext_vector_type(4)));
+            const v4f q = {v[0], v[1], v[2], v[3]};
+            __builtin_nontemporal_store(q, reinterpret_cast<v4f *>(p));
         } else {
             uint16_t hb[4];
 #pragma unroll
@@ -72,8 +75,9 @@ __device__ __forceinline__ void store4(T *p, const float v[4], int nvalid)
                 T t = from_f32<T>(v[c]);
                 hb[c] = *reinterpret_cast<uint16_t *>(&t);
             }
-            *reinterpret_cast<uint2 *>(p) = make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16),
-                                                       (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
+            typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+            const v2u q = {(uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16)};
+            __builtin_nontemporal_store(q, reinterpret_cast<v2u *>(p));
         }
     } else {
 #pragma unroll
