@@ -14,11 +14,31 @@
 //   G_z[s] = A[s+1] - A[s-1],  G_y[s] = (S_z B)[s],  G_x[s] = (S_z C)[s].
 // HBM traffic is one read and one write per voxel.
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 
 namespace harpia {
 namespace edge_detail {
+
+// Four consecutive outputs: one non-temporal 16-byte store when all 4 are
+// inside the region and aligned (f32 output; the kernel never reads it
+// back), else element by element.
+template <typename Tout>
+__device__ __forceinline__ void put4(Tout *p, const float v[4], int nvalid)
+{
+    if constexpr (std::is_same<Tout, float>::value) {
+        if (nvalid == 4 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+            typedef float v4f __attribute__((ext_vector_type(4)));
+            const v4f q = {v[0], v[1], v[2], v[3]};
+            __builtin_nontemporal_store(q, reinterpret_cast<v4f *>(p));
+            return;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        if (c < nvalid) p[c] = from_f32<Tout>(v[c]);
+}
 
 constexpr int kNT = 512;
 constexpr int kTX = 128, kTY = 16;  // one 4-column quad per thread
@@ -122,13 +142,15 @@ __global__ __launch_bounds__(kNT) void edge_kernel(ChunkArgs a, int zlen, int ti
             if (j >= 2 && nvalid > 0) {
                 constexpr int s0 = (u + 1) % 3, s1 = (u + 2) % 3, s2 = u;
                 const int64_t zl = zo0 + j - 2 - a.out_o[0];
+                float m[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const float gz = rA[s2][c] - rA[s0][c];
                     const float gy = smooth3<PREWITT>(rB[s0][c], rB[s1][c], rB[s2][c]);
                     const float gx = smooth3<PREWITT>(rC[s0][c], rC[s1][c], rC[s2][c]);
-                    if (c < nvalid) outp[zl * a.out_sz + c] = from_f32<Tout>(sqrtf(fmaf(gz, gz, fmaf(gy, gy, gx * gx))));
+                    m[c] = sqrtf(fmaf(gz, gz, fmaf(gy, gy, gx * gx)));
                 }
+                put4(outp + zl * a.out_sz, m, nvalid);
             }
         });
     }
